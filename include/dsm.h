@@ -1,0 +1,355 @@
+/*
+ * dsm.h - dynamic sparse matrices on one MI355X (gfx950).
+ *
+ * A C ABI over a "dynamic matrix": one handle that holds a sparse matrix in
+ * exactly one active storage format at a time and can switch that format at
+ * run time (the DynamicMatrix of arXiv 2209.06478, Section III-A, whose
+ * active state changes through activate()/convert, Sections III-A, III-B
+ * and IV-B).  On top of the handle sit SpMV (Section III-D, "multiply"),
+ * format selection by timed profiling runs (Section V-E, the naive
+ * auto-tuner), and the conjugate-gradient loop of HPCG with the
+ * preconditioner disabled (Sections II-B and IV-B).
+ *
+ * Conventions shared by every entry point:
+ *   - Indices are int32 (row pointers, rows, columns, offsets); linear slot
+ *     indices inside the library are 64-bit.
+ *   - A "device pointer" is memory on the handle's GPU (hipMalloc'd, e.g. a
+ *     torch CUDA tensor's data_ptr()); a "host pointer" is ordinary memory.
+ *     Vectors passed to the library are never owned by it (the paper's
+ *     unmanaged containers, Section IV-A): the caller allocates and frees
+ *     them and keeps them alive until the stream work that uses them is done.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     Asynchronous calls enqueue work on it and return; calls marked
+ *     "blocking" synchronise it before returning.
+ *   - Every call returns a dsm_status.  No C++ exception and no abort cross
+ *     this boundary.  On failure dsm_last_error() returns a thread-local
+ *     message describing the most recent error of the calling thread.
+ *   - Handles are not thread-safe; distinct handles may be used concurrently
+ *     on distinct streams.
+ */
+#ifndef DSM_H
+#define DSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dsm_ctx_s *dsm_ctx;
+typedef struct dsm_matrix_s *dsm_matrix;
+typedef struct dsm_server_s *dsm_server;
+typedef int32_t dsm_status;
+
+/* Storage formats.  Stable integer indices: activate/convert accept them
+ * (Section III-A lets the active state be chosen by enum or by index). */
+typedef enum {
+    DSM_COO = 0, /* coordinate list, sorted by (row, col) (Section II-A)        */
+    DSM_CSR = 1, /* compressed rows, ascending columns per row (Section II-A)   */
+    DSM_DIA = 2, /* diagonals: offsets + one stored column per diagonal (II-A)  */
+    DSM_ELL = 3, /* ELLPACK: K = longest row, K slots per row (Section VI)      */
+    DSM_HYB = 4, /* ELL of width K_h + COO overflow (Section VI)                */
+    DSM_HDC = 5  /* DIA over well-filled diagonals + CSR remainder (Section VI) */
+} dsm_format;
+#define DSM_NUM_FORMATS 6
+
+/* Element types of matrix values and of dense vectors. */
+typedef enum { DSM_F64 = 0, DSM_F32 = 1, DSM_BF16 = 2 } dsm_dtype;
+
+/* Status codes. */
+#define DSM_OK 0
+#define DSM_E_INVALID (-1)       /* bad argument or malformed structure         */
+#define DSM_E_NOMEM (-2)         /* device allocation failed or budget exceeded */
+#define DSM_E_INFEASIBLE (-3)    /* padding above max_pad_ratio                 */
+#define DSM_E_UNSUPPORTED (-4)   /* operation not defined for these arguments   */
+#define DSM_E_NOT_CONVERGED (-5) /* iteration limit reached, result filled      */
+#define DSM_E_BREAKDOWN (-6)     /* p.q <= 0 or a non-finite scalar in CG       */
+#define DSM_E_PENDING (-7)       /* server request not finished yet             */
+#define DSM_E_DEVICE (-8)        /* HIP runtime error                           */
+
+const char *dsm_status_string(dsm_status s);
+/* Message of the calling thread's most recent error ("" if none).  The
+ * pointer stays valid until the thread's next dsm_* call. */
+const char *dsm_last_error(void);
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int32_t dsm_version(void);
+
+/* ------------------------------------------------------------------ */
+/* Context: device binding and HBM budget.                             */
+/* ------------------------------------------------------------------ */
+/* Binds to HIP device `device`.  hbm_budget_bytes caps the bytes held by
+ * all matrices of this context (payloads plus solver workspaces); 0 means
+ * no cap beyond what hipMalloc can give.  Exceeding it fails with
+ * DSM_E_NOMEM before anything is allocated. */
+dsm_status dsm_ctx_create(int device, size_t hbm_budget_bytes, dsm_ctx *out);
+/* Frees the context.  All its matrices must have been destroyed. */
+dsm_status dsm_ctx_destroy(dsm_ctx ctx);
+/* Bytes currently charged against the budget. */
+dsm_status dsm_ctx_bytes_in_use(dsm_ctx ctx, size_t *out);
+
+/* ------------------------------------------------------------------ */
+/* Creation (deep copy in, Section III-B).                             */
+/* ------------------------------------------------------------------ */
+/* Builds a handle whose active format is CSR with FP64 values from
+ * canonical CSR arrays: row_ptr[nrows+1] (row_ptr[0] = 0, non-decreasing,
+ * row_ptr[nrows] = nnz), col[nnz] strictly ascending inside each row and in
+ * [0, ncols), val[nnz].  The arrays are host pointers if on_device == 0,
+ * device pointers otherwise; they are copied and remain owned by the caller
+ * (free them once `stream` has completed).  The structure is validated on
+ * the device; a violation (including duplicate columns) gives
+ * DSM_E_INVALID and no handle.  Blocking. */
+dsm_status dsm_create_csr(dsm_ctx ctx, int64_t nrows, int64_t ncols, int64_t nnz,
+                          const int32_t *row_ptr, const int32_t *col, const double *val,
+                          int on_device, void *stream, dsm_matrix *out);
+
+/* Same from COO triplets row[nnz], col[nnz], val[nnz].  If `sorted` is
+ * non-zero the triplets must already be in ascending (row, col) order;
+ * otherwise they are sorted on the device first.  Duplicate (row, col)
+ * pairs give DSM_E_INVALID.  The active format is CSR.  Blocking. */
+dsm_status dsm_create_coo(dsm_ctx ctx, int64_t nrows, int64_t ncols, int64_t nnz,
+                          const int32_t *row, const int32_t *col, const double *val,
+                          int sorted, int on_device, void *stream, dsm_matrix *out);
+
+/* Synchronises the handle's last stream, then frees everything it owns. */
+dsm_status dsm_matrix_destroy(dsm_matrix m);
+
+/* ------------------------------------------------------------------ */
+/* Format switching (Section III-B "convert", Section IV-B in-place    */
+/* conversion of the dynamic matrix).                                  */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    dsm_dtype value_dtype; /* values after conversion: F64, F32 (round to nearest
+                              even) or BF16 (round to nearest even of the F32
+                              value).  Narrowing is one-way. */
+    double hdc_theta;      /* HDC keeps diagonal d in DIA iff count_d >= theta*L_d
+                              (L_d = in-range positions on d); <= 0 means 0.5 */
+    double max_pad_ratio;  /* DIA/ELL refuse (DSM_E_INFEASIBLE) when stored slots
+                              exceed max_pad_ratio * nnz; <= 0 means 16 */
+    int32_t hyb_width;     /* HYB ELL width K_h; < 0 means the default rule (the
+                              largest k reached by at least ceil(nrows/3) rows) */
+} dsm_convert_opts;
+
+/* Fills *o with the defaults (value_dtype = the handle's current dtype is
+ * NOT implied: defaults use F64). */
+void dsm_convert_opts_default(dsm_convert_opts *o);
+
+/* Converts the handle in place to `fmt` (opts NULL = defaults with the
+ * handle's current value dtype).  Transactional: the new payload is built
+ * completely, then the old one is freed; on any error the old format stays
+ * active and usable.  Peak memory is old + new payload.  Blocking (sizes of
+ * the new payload are read back from the device). */
+dsm_status dsm_convert(dsm_matrix m, dsm_format fmt, const dsm_convert_opts *opts, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Inspection and export (HostMirror deep copy, Section III-C).        */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t format;      /* dsm_format */
+    int32_t value_dtype; /* dsm_dtype */
+    int64_t nrows, ncols, nnz;
+    int64_t ndiag;       /* DIA: diagonals; HDC: DIA-part diagonals; else 0 */
+    int64_t ell_width;   /* ELL: K; HYB: K_h; else 0 */
+    int64_t coo_nnz;     /* COO: nnz; HYB: entries in the COO part; else 0 */
+    int64_t csr_nnz;     /* CSR: nnz; HDC: entries in the CSR part; else 0 */
+    int64_t bytes;       /* device bytes held by the active payload */
+    int64_t pitch;       /* device row pitch of DIA/ELL arrays (>= nrows) */
+    double hdc_theta;
+} dsm_info;
+
+dsm_status dsm_get_info(dsm_matrix m, dsm_info *out);
+
+/* Host buffers for dsm_export; size each from dsm_info (value arrays use
+ * the handle's value dtype: 8, 4 or 2 bytes per element).  Pointers not
+ * used by the active format are ignored and may be NULL.  DIA/ELL arrays
+ * are exported with pitch = nrows, diagonal-/slot-major: element (k, i) at
+ * k*nrows + i.
+ *   COO: row, col, val (coo_nnz)
+ *   CSR: row_ptr (nrows+1), col, val (csr_nnz)
+ *   DIA: offsets (ndiag), dia_val (ndiag*nrows)
+ *   ELL: ell_col, ell_val (ell_width*nrows; empty slot: col -1, value +0)
+ *   HYB: ell_col, ell_val (K_h*nrows) + row, col, val (coo_nnz)
+ *   HDC: offsets, dia_val (ndiag*nrows) + row_ptr, col, val (csr_nnz) */
+typedef struct {
+    int32_t *row_ptr;
+    int32_t *row;
+    int32_t *col;
+    void *val;
+    int32_t *offsets;
+    void *dia_val;
+    int32_t *ell_col;
+    void *ell_val;
+} dsm_export_bufs;
+
+/* Copies the canonical arrays of the active format to host memory.
+ * Blocking. */
+dsm_status dsm_export(dsm_matrix m, const dsm_export_bufs *bufs, void *stream);
+
+/* Structure statistics of the matrix (computed on the device from the
+ * active payload's row structure): out[0..4] = max row length, min row
+ * length, sum of lengths, sum of squared lengths, number of empty rows;
+ * out[5 + b] for b in 0..32 = number of rows with length in [2^(b-1), 2^b)
+ * (bin 0 = empty rows).  `out` is a host array of 38 int64.  Blocking. */
+dsm_status dsm_row_stats(dsm_matrix m, int64_t *out, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* SpMV (Section III-D "multiply").                                    */
+/* ------------------------------------------------------------------ */
+/* y = A x with x (ncols) and y (nrows) device vectors of `vec_dtype` (F64
+ * or F32; they must not alias).  Products are accumulated in vec_dtype;
+ * stored F32/BF16 values are widened exactly.  y is written, not read.
+ * Asynchronous on `stream`. */
+dsm_status dsm_spmv(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, void *stream);
+
+/* Kernel variant used for SpMV in formats that have several (CSR: 0 =
+ * adaptive row blocks, 1..7 = vector kernel with 2^v lanes per row; other
+ * formats: 0).  Set by dsm_select or directly. */
+dsm_status dsm_set_variant(dsm_matrix m, int32_t variant);
+dsm_status dsm_get_variant(dsm_matrix m, int32_t *variant);
+
+/* ------------------------------------------------------------------ */
+/* Format selection by timed profiling runs (Section V-E).             */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t warmup;        /* untimed runs per candidate (default 3)          */
+    int32_t reps;          /* timed runs per candidate, median kept (def. 20) */
+    int32_t use_cache;     /* reuse a previous choice for the same structure  */
+    int32_t tune_variant;  /* also time CSR kernel variants (default 1)       */
+    dsm_dtype vec_dtype;   /* vector type the SpMVs are timed with            */
+    dsm_dtype value_dtype; /* value type of every candidate                   */
+    double max_pad_ratio;  /* as in dsm_convert_opts                          */
+    double bytes_prefilter;/* skip candidates moving more than this many times
+                              the bytes of the leanest candidate (default 2)  */
+} dsm_select_opts;
+
+void dsm_select_opts_default(dsm_select_opts *o);
+
+typedef struct {
+    int32_t chosen;                      /* dsm_format now active           */
+    int32_t chosen_variant;              /* kernel variant now active       */
+    int32_t cache_hit;                   /* 1 if the cached choice was used */
+    int32_t status[DSM_NUM_FORMATS];     /* per candidate: DSM_OK, or why it
+                                            was skipped (INFEASIBLE, NOMEM,
+                                            UNSUPPORTED = not in mask or
+                                            pruned by bytes)                */
+    double median_us[DSM_NUM_FORMATS];   /* median SpMV time (0 if skipped) */
+    double convert_us[DSM_NUM_FORMATS];  /* conversion time from CSR        */
+    double bytes[DSM_NUM_FORMATS];       /* algorithmic bytes per SpMV      */
+} dsm_select_report;
+
+/* Converts the handle to each candidate of `candidate_mask` (bit f =
+ * format f) that passes the feasibility prefilter, times SpMV, and leaves
+ * the fastest one active (ties within 2% go to fewer bytes).  The original
+ * payload is kept until the end, so a failure leaves the handle unchanged.
+ * Blocking. */
+dsm_status dsm_select(dsm_matrix m, uint32_t candidate_mask, const dsm_select_opts *opts,
+                      dsm_select_report *report, void *stream);
+
+/* Drops all cached selections of a context. */
+dsm_status dsm_select_cache_clear(dsm_ctx ctx);
+
+/* ------------------------------------------------------------------ */
+/* Conjugate gradients (HPCG's CG without preconditioner, Section IV-B)*/
+/* ------------------------------------------------------------------ */
+typedef enum {
+    DSM_CG_F64 = 0,   /* FP64 vectors, dots and updates; SpMV accumulates in
+                         FP64 over the stored values (any value dtype)       */
+    DSM_CG_IR = 1     /* iterative refinement: outer FP64 residual, dots and
+                         update; inner CG in FP32 vectors with FP32 SpMV
+                         accumulation and FP64 dot accumulation (values must
+                         be F32 or BF16)                                      */
+} dsm_cg_mode;
+
+typedef struct {
+    double tol;          /* stop when ||r|| <= tol * ||r0|| (2-norms)          */
+    int64_t maxit;       /* SpMV limit (outer iterations for F64; inner total
+                            for IR); <= 0 means min(10*n, 20000)              */
+    int32_t mode;        /* dsm_cg_mode                                        */
+    double inner_tol;    /* IR: inner relative tolerance (default 1e-4)        */
+    int32_t check_every; /* iterations between host checks of the device
+                            convergence flag (default: chosen by size)        */
+    int32_t max_outer;   /* IR: outer iteration limit (default 50)             */
+} dsm_cg_opts;
+
+void dsm_cg_opts_default(dsm_cg_opts *o);
+
+typedef struct {
+    int64_t iters;          /* SpMVs inside the iteration (F64), or total inner
+                               iterations (IR)                                  */
+    int64_t outer_iters;    /* IR refinement steps (F64: 0)                     */
+    double relres;          /* final recursive (F64) or true outer (IR) relres  */
+    double relres_true;     /* ||b - A x|| / ||b|| recomputed in FP64 at the end */
+    int32_t status;         /* DSM_OK, DSM_E_NOT_CONVERGED or DSM_E_BREAKDOWN   */
+} dsm_cg_result;
+
+/* Solves A x = b for square A.  b and x are FP64 device vectors of length
+ * nrows; x holds x0 on entry and the last iterate on return.  The result is
+ * filled for OK, NOT_CONVERGED and BREAKDOWN.  Blocking. */
+dsm_status dsm_cg_solve(dsm_matrix m, const double *b, double *x, const dsm_cg_opts *opts,
+                        dsm_cg_result *result, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Batched solves: many independent CG problems in one launch.          */
+/* ------------------------------------------------------------------ */
+/* Solves A_k x_k = b_k for k < count with plain FP64 CG, each system with
+ * its own matrix handle (square; any format), device vectors b[k], x[k]
+ * (x holds x0) and tolerance/maxit from opts[k] (mode must be F64).
+ * Systems small enough run whole inside one persistent workgroup each;
+ * larger ones are solved one after another on `stream`.  Each system's
+ * result is bitwise the same as when it is solved alone.  Blocking. */
+dsm_status dsm_cg_solve_batched(int32_t count, const dsm_matrix *mats, const double *const *b,
+                                double *const *x, const dsm_cg_opts *opts,
+                                dsm_cg_result *results, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Serving: continuous batching of CG solves under an HBM budget.       */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t slots;           /* requests in flight at once (default 64)        */
+    size_t hbm_budget;       /* bytes of matrices + workspaces in flight
+                                (0 = the context's budget or unlimited)       */
+    int32_t streams;         /* HIP streams for large requests (default 4)     */
+    int64_t small_rows;      /* requests with at most this many rows go to the
+                                persistent batched kernel (default 40000)     */
+    int32_t batch_max;       /* max requests per persistent launch (def. 256)  */
+} dsm_server_opts;
+
+void dsm_server_opts_default(dsm_server_opts *o);
+
+typedef struct {
+    double arrival_s;  /* submit time, seconds on the server's clock */
+    double start_s;    /* first device work enqueued                  */
+    double finish_s;   /* result known on the host                    */
+} dsm_timestamps;
+
+/* Creates a server with its own scheduler thread. */
+dsm_status dsm_server_create(dsm_ctx ctx, const dsm_server_opts *opts, dsm_server *out);
+
+/* Queues a solve of m x = b (b, x device FP64 vectors; x holds x0).  The
+ * matrix and both vectors must stay alive and untouched until the request
+ * completes.  Requests whose footprint exceeds the server budget fail with
+ * DSM_E_NOMEM at submit.  *ticket identifies the request. */
+dsm_status dsm_server_submit(dsm_server s, dsm_matrix m, const double *b, double *x,
+                             const dsm_cg_opts *opts, uint64_t *ticket);
+
+/* DSM_E_PENDING while the request runs; otherwise DSM_OK and the result and
+ * timestamps are filled (the request's solver status is in result->status).
+ * A finished ticket can be polled again until dsm_server_destroy. */
+dsm_status dsm_server_poll(dsm_server s, uint64_t ticket, dsm_cg_result *result,
+                           dsm_timestamps *ts);
+
+/* Blocks until the request finishes, then behaves like dsm_server_poll. */
+dsm_status dsm_server_wait(dsm_server s, uint64_t ticket, dsm_cg_result *result,
+                           dsm_timestamps *ts);
+
+/* Seconds on the server's clock (the clock of dsm_timestamps). */
+double dsm_server_now(dsm_server s);
+
+/* Waits for every queued request, stops the scheduler and frees the server. */
+dsm_status dsm_server_destroy(dsm_server s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSM_H */

@@ -336,13 +336,18 @@ i32 orc_hyb_width(i64 nrows, const i32 *rp)
     if (nrows == 0) return 0;
     i64 need = (nrows + 2) / 3;
     i32 K = orc_ell_width(nrows, rp);
-    for (i32 k = K; k > 0; k--) {
-        i64 cnt = 0;
-        for (i64 i = 0; i < nrows; i++)
-            if (rp[i + 1] - rp[i] >= k) cnt++;
-        if (cnt >= need) return k;
+    /* count[k] = rows of length exactly k; walking k down accumulates the
+     * number of rows with length >= k */
+    i64 *count = (i64 *)calloc((size_t)K + 1, sizeof(i64));
+    for (i64 i = 0; i < nrows; i++) count[rp[i + 1] - rp[i]]++;
+    i64 ge = 0;
+    i32 k = K;
+    for (; k > 0; k--) {
+        ge += count[k];
+        if (ge >= need) break;
     }
-    return 0;
+    free(count);
+    return k;
 }
 
 /* Number of entries that overflow into the COO part of HYB(K_h). */

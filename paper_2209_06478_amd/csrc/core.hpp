@@ -1,0 +1,132 @@
+// Host-side objects of libdsm: the context (device + HBM budget), the
+// dynamic matrix handle with its single active payload, and the interfaces
+// between the translation units (scan, conversion, SpMV, CG, selection).
+#pragma once
+
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+struct dsm_ctx_s {
+    int device = 0;
+    size_t budget = 0;                  // 0: no cap
+    std::atomic<size_t> in_use{0};
+    std::atomic<int> live_matrices{0};
+    std::mutex cache_mu;                // selection cache
+    std::map<std::string, std::pair<int, int>> select_cache;  // fingerprint -> (format, variant)
+};
+
+namespace dsm {
+
+// Device memory charged against the context budget.
+void *dev_alloc(dsm_ctx ctx, size_t bytes);
+void dev_free(dsm_ctx ctx, void *p, size_t bytes);
+
+// One storage format's arrays.  HYB uses the ELL and COO members, HDC the
+// DIA and CSR members; the others use their own.
+struct Payload {
+    int fmt = DSM_CSR;
+    int vdt = DSM_F64;
+    // CSR (HDC remainder)
+    i32 *rp = nullptr, *col = nullptr;
+    void *val = nullptr;
+    i64 csr_nnz = 0;
+    i32 *rblocks = nullptr;  // adaptive row blocks: nrblocks + 1 row indices
+    i64 nrblocks = 0;
+    // COO (HYB overflow)
+    i32 *crow = nullptr, *ccol = nullptr;
+    void *cval = nullptr;
+    i64 coo_nnz = 0;
+    // DIA (HDC)
+    i32 *offs = nullptr;
+    void *dval = nullptr;
+    i64 ndiag = 0;
+    // ELL (HYB)
+    i32 *ecol = nullptr;
+    void *evl = nullptr;
+    i64 K = 0;
+    i64 pitch = 0;
+    double theta = 0.5;
+    // owned allocations
+    std::vector<std::pair<void *, size_t>> bufs;
+    size_t bytes = 0;
+
+    void *alloc(dsm_ctx ctx, size_t b) {
+        if (b == 0) b = 16;
+        void *p = dev_alloc(ctx, b);
+        bufs.push_back({p, b});
+        bytes += b;
+        return p;
+    }
+    void release(dsm_ctx ctx) {
+        for (auto &pb : bufs) dev_free(ctx, pb.first, pb.second);
+        bufs.clear();
+        bytes = 0;
+        *this = Payload();
+    }
+};
+
+// Scratch buffers the SpMV/CG paths reuse between calls.
+struct Workspace {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace dsm
+
+struct dsm_matrix_s {
+    dsm_ctx ctx = nullptr;
+    int64_t nrows = 0, ncols = 0, nnz = 0;
+    dsm::Payload P;
+    int variant = 0;
+    hipStream_t last_stream = nullptr;
+    dsm::Workspace ws;   // SpMV scratch (COO tile carries)
+    dsm::Workspace cgws; // CG vectors and scalars
+};
+
+namespace dsm {
+
+// Grows (never shrinks) a workspace; contents are not preserved.
+void *ws_get(dsm_ctx ctx, Workspace &w, size_t bytes);
+void ws_release(dsm_ctx ctx, Workspace &w);
+
+// ---------------------------------------------------------------- scan.hip
+// Exclusive prefix sum of n int32 counts into out[0..n] (out[n] = total);
+// returns the total (blocking read-back when `want_total`).
+i64 exclusive_scan_i32(dsm_ctx ctx, const i32 *in, i32 *out, i64 n, hipStream_t s, bool want_total);
+i64 exclusive_scan_i64(dsm_ctx ctx, const i64 *in, i64 *out, i64 n, hipStream_t s, bool want_total);
+// max over n int32 values (blocking)
+i32 reduce_max_i32(dsm_ctx ctx, const i32 *in, i64 n, hipStream_t s);
+
+// ---------------------------------------------------------------- convert.hip
+// Validates canonical CSR on the device; fails with DSM_E_INVALID.
+void validate_csr(dsm_ctx ctx, i64 nrows, i64 ncols, i64 nnz, const i32 *rp, const i32 *col,
+                  hipStream_t s);
+// Builds the adaptive row blocks of a CSR part.
+void build_row_blocks(dsm_ctx ctx, Payload &P, i64 nrows, hipStream_t s);
+// Any payload -> canonical CSR payload (values keep their dtype).
+Payload to_csr(dsm_matrix m, const Payload &src, hipStream_t s);
+// Canonical CSR payload -> payload of `fmt` with values cast to `vdt`.
+Payload from_csr(dsm_matrix m, const Payload &csr, int fmt, int vdt, const dsm_convert_opts &o,
+                 hipStream_t s);
+// Same dtype cast of a CSR payload (returns a new CSR payload).
+Payload cast_csr(dsm_matrix m, const Payload &csr, int vdt, hipStream_t s);
+// COO triplets (sorted or not) -> canonical CSR payload with F64 values.
+Payload coo_to_csr_payload(dsm_matrix m, const i32 *row, const i32 *col, const double *val,
+                           i64 nnz, bool sorted, hipStream_t s);
+void row_stats(dsm_matrix m, i64 *out, hipStream_t s);
+
+// ---------------------------------------------------------------- spmv.hip
+// y (=|+=) A x for one payload; vector dtype F64 or F32.
+void spmv(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant,
+          hipStream_t s);
+// Algorithmic bytes one SpMV must move (x read once, y written once).
+double spmv_bytes(const dsm_matrix_s *m, const Payload &P, int vec_dtype);
+// Number of CSR kernel variants (index 0 = adaptive).
+constexpr int CSR_VARIANTS = 8;
+
+}  // namespace dsm

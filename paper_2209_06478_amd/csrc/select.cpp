@@ -1,0 +1,265 @@
+// Format selection by profiling runs: the paper's naive auto-tuner
+// (Section V-E) times SpMV in every candidate format and keeps the fastest.
+// Here it runs per matrix handle on the GPU, also picks the kernel variant
+// (CSR lane grouping, XCD-aware tile order), prunes candidates that cannot
+// win on bytes or that pad too much, and caches the decision per context
+// under a fingerprint of the row structure.
+#include <algorithm>
+#include <cmath>
+#include <sstream>
+#include <vector>
+
+#include "core.hpp"
+
+namespace dsm {
+
+Payload build_format(dsm_matrix m, int fmt, const dsm_convert_opts &o, hipStream_t s);
+
+template <class T>
+__global__ void k_fill_value(i64 n, T *y, T v) {
+    i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = v;
+}
+
+static std::string fingerprint(dsm_matrix m, int vdt, int vec) {
+    i64 st[38];
+    row_stats(m, st, m->last_stream);
+    std::ostringstream os;
+    os << m->nrows << "x" << m->ncols << ":" << m->nnz << ":v" << vdt << ":x" << vec;
+    for (int i = 0; i < 38; i++) os << "," << st[i];
+    return os.str();
+}
+
+// Median time (us) of `reps` SpMVs after `warmup` untimed ones.
+static double time_spmv(dsm_matrix m, const Payload &P, int variant, const void *x, void *y, int vec, int warmup,
+                        int reps, hipStream_t s) {
+    for (int i = 0; i < warmup; i++) spmv(m, P, x, y, vec, variant, s);
+    std::vector<hipEvent_t> ev(2 * reps);
+    for (auto &e : ev) DSM_HIP(hipEventCreate(&e));
+    for (int i = 0; i < reps; i++) {
+        DSM_HIP(hipEventRecord(ev[2 * i], s));
+        spmv(m, P, x, y, vec, variant, s);
+        DSM_HIP(hipEventRecord(ev[2 * i + 1], s));
+    }
+    DSM_HIP(hipStreamSynchronize(s));
+    std::vector<double> t(reps);
+    for (int i = 0; i < reps; i++) {
+        float ms = 0;
+        DSM_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+        t[i] = ms * 1000.0;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    std::sort(t.begin(), t.end());
+    return reps ? t[reps / 2] : 0.0;
+}
+
+// preference order for exact ties: CSR, DIA, ELL, HYB, HDC, COO
+static int rank_of(int f) {
+    static const int r[6] = {5, 0, 1, 2, 3, 4};
+    return r[f];
+}
+
+void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_select_report *rep, hipStream_t s) {
+    dsm_ctx ctx = m->ctx;
+    dsm_select_report R{};
+    for (int f = 0; f < DSM_NUM_FORMATS; f++) R.status[f] = DSM_E_UNSUPPORTED;
+    const int vec = o.vec_dtype;
+    DSM_CHECK(vec == DSM_F64 || vec == DSM_F32, DSM_E_INVALID, "vec_dtype must be F64 or F32");
+    mask &= (1u << DSM_NUM_FORMATS) - 1;
+    DSM_CHECK(mask != 0, DSM_E_INVALID, "empty candidate mask");
+    m->last_stream = s;
+    const std::string key = fingerprint(m, o.value_dtype, vec) + ":m" + std::to_string(mask);
+
+    dsm_convert_opts co;
+    dsm_convert_opts_default(&co);
+    co.value_dtype = o.value_dtype;
+    co.max_pad_ratio = o.max_pad_ratio;
+
+    if (o.use_cache) {
+        std::pair<int, int> hit{-1, 0};
+        {
+            std::lock_guard<std::mutex> lk(ctx->cache_mu);
+            auto it = ctx->select_cache.find(key);
+            if (it != ctx->select_cache.end()) hit = it->second;
+        }
+        if (hit.first >= 0) {
+            if (!(m->P.fmt == hit.first && m->P.vdt == o.value_dtype)) {
+                Payload np = build_format(m, hit.first, co, s);
+                DSM_HIP(hipStreamSynchronize(s));
+                m->P.release(ctx);
+                m->P = np;
+            }
+            m->variant = hit.second;
+            R.chosen = hit.first;
+            R.chosen_variant = hit.second;
+            R.cache_hit = 1;
+            R.status[hit.first] = DSM_OK;
+            R.bytes[hit.first] = spmv_bytes(m, m->P, vec);
+            if (rep) *rep = R;
+            return;
+        }
+    }
+
+    const size_t xs = dtype_size(vec);
+    void *x = dev_alloc(ctx, xs * (size_t)std::max<i64>(m->ncols, 1));
+    void *y = nullptr;
+    try {
+        y = dev_alloc(ctx, xs * (size_t)std::max<i64>(m->nrows, 1));
+    } catch (...) {
+        dev_free(ctx, x, xs * (size_t)std::max<i64>(m->ncols, 1));
+        throw;
+    }
+    const unsigned gx = grid_for(m->ncols, 256);
+    if (vec == DSM_F64) hipLaunchKernelGGL(k_fill_value<double>, dim3(gx), dim3(256), 0, s, m->ncols, (double *)x, 1.0);
+    else hipLaunchKernelGGL(k_fill_value<float>, dim3(gx), dim3(256), 0, s, m->ncols, (float *)x, 1.0f);
+
+    Payload best;
+    bool have_best = false, best_is_current = false;
+    double best_t = 0, best_bytes = 0, min_bytes = 0;
+    int best_f = -1, best_v = 0;
+    static const int order[6] = {DSM_CSR, DSM_DIA, DSM_ELL, DSM_HYB, DSM_HDC, DSM_COO};
+    auto cleanup = [&] {
+        (void)hipStreamSynchronize(s);
+        dev_free(ctx, x, xs * (size_t)std::max<i64>(m->ncols, 1));
+        dev_free(ctx, y, xs * (size_t)std::max<i64>(m->nrows, 1));
+    };
+    try {
+        for (int f : order) {
+            if (!(mask & (1u << f))) continue;
+            // candidate payload: the current one if it already matches
+            Payload cand;
+            bool is_current = m->P.fmt == f && m->P.vdt == o.value_dtype;
+            hipEvent_t c0, c1;
+            DSM_HIP(hipEventCreate(&c0));
+            DSM_HIP(hipEventCreate(&c1));
+            DSM_HIP(hipEventRecord(c0, s));
+            if (!is_current) {
+                try {
+                    cand = build_format(m, f, co, s);
+                } catch (const Error &e) {
+                    (void)hipEventDestroy(c0);
+                    (void)hipEventDestroy(c1);
+                    if (e.status == DSM_E_INFEASIBLE || e.status == DSM_E_NOMEM) {
+                        R.status[f] = e.status;
+                        continue;
+                    }
+                    throw;
+                }
+            }
+            DSM_HIP(hipEventRecord(c1, s));
+            DSM_HIP(hipStreamSynchronize(s));
+            float cms = 0;
+            DSM_HIP(hipEventElapsedTime(&cms, c0, c1));
+            (void)hipEventDestroy(c0);
+            (void)hipEventDestroy(c1);
+            R.convert_us[f] = is_current ? 0.0 : cms * 1000.0;
+            const Payload &P = is_current ? m->P : cand;
+            const double bytes = spmv_bytes(m, P, vec);
+            R.bytes[f] = bytes;
+            if (min_bytes > 0 && bytes > o.bytes_prefilter * min_bytes) {
+                R.status[f] = DSM_E_UNSUPPORTED;  // pruned: cannot win on bytes
+                if (!is_current) cand.release(ctx);
+                continue;
+            }
+            min_bytes = min_bytes > 0 ? std::min(min_bytes, bytes) : bytes;
+            // kernel variants of this format
+            std::vector<int> variants{0};
+            if (o.tune_variant) {
+                if (f == DSM_CSR) variants = {0, 7, 2, 3, 4, 5, 6};
+                else if (f == DSM_DIA || f == DSM_ELL) variants = {0, 1};
+            }
+            double tf = 0;
+            int vf = 0;
+            for (int v : variants) {
+                double t = time_spmv(m, P, v, x, y, vec, o.warmup, o.reps, s);
+                if (v == variants[0] || t < tf) {
+                    tf = t;
+                    vf = v;
+                }
+            }
+            R.status[f] = DSM_OK;
+            R.median_us[f] = tf;
+            bool better = !have_best;
+            if (have_best) {
+                if (tf < best_t * 0.98) better = true;
+                else if (tf <= best_t * 1.02) {
+                    if (bytes < best_bytes) better = true;
+                    else if (bytes == best_bytes && rank_of(f) < rank_of(best_f)) better = true;
+                }
+            }
+            if (better) {
+                if (have_best && !best_is_current) best.release(ctx);
+                if (is_current) {
+                    best_is_current = true;
+                } else {
+                    best = cand;
+                    best_is_current = false;
+                }
+                have_best = true;
+                best_t = tf;
+                best_bytes = bytes;
+                best_f = f;
+                best_v = vf;
+            } else if (!is_current) {
+                cand.release(ctx);
+            }
+        }
+    } catch (...) {
+        if (have_best && !best_is_current) best.release(ctx);
+        cleanup();
+        throw;
+    }
+    cleanup();
+    DSM_CHECK(have_best, DSM_E_INFEASIBLE, "no candidate format is feasible");
+    if (!best_is_current) {
+        m->P.release(ctx);
+        m->P = best;
+    }
+    m->variant = best_v;
+    R.chosen = best_f;
+    R.chosen_variant = best_v;
+    {
+        std::lock_guard<std::mutex> lk(ctx->cache_mu);
+        ctx->select_cache[key] = {best_f, best_v};
+    }
+    if (rep) *rep = R;
+}
+
+}  // namespace dsm
+
+using namespace dsm;
+
+DSM_API void dsm_select_opts_default(dsm_select_opts *o) {
+    if (!o) return;
+    o->warmup = 3;
+    o->reps = 20;
+    o->use_cache = 1;
+    o->tune_variant = 1;
+    o->vec_dtype = DSM_F64;
+    o->value_dtype = DSM_F64;
+    o->max_pad_ratio = 16.0;
+    o->bytes_prefilter = 2.0;
+}
+
+DSM_API dsm_status dsm_select(dsm_matrix m, uint32_t candidate_mask, const dsm_select_opts *opts,
+                              dsm_select_report *report, void *stream) {
+    return guard([&] {
+        DSM_CHECK(m && m->ctx, DSM_E_INVALID, "null matrix handle");
+        DSM_HIP(hipSetDevice(m->ctx->device));
+        dsm_select_opts o;
+        dsm_select_opts_default(&o);
+        if (opts) o = *opts;
+        DSM_CHECK(o.reps >= 1 && o.warmup >= 0, DSM_E_INVALID, "reps must be >= 1");
+        DSM_CHECK(o.value_dtype >= DSM_F64 && o.value_dtype <= DSM_BF16, DSM_E_INVALID, "bad value dtype");
+        if (o.bytes_prefilter <= 0) o.bytes_prefilter = 2.0;
+        select_format(m, candidate_mask, o, report, (hipStream_t)stream);
+    });
+}
+
+DSM_API dsm_status dsm_select_cache_clear(dsm_ctx ctx) {
+    return guard([&] {
+        DSM_CHECK(ctx, DSM_E_INVALID, "null context");
+        std::lock_guard<std::mutex> lk(ctx->cache_mu);
+        ctx->select_cache.clear();
+    });
+}

@@ -1,0 +1,397 @@
+// SpMV y = A x for every storage format ("multiply" of the dynamic matrix).
+//
+// All kernels are bandwidth kernels: no matrix-core work, coalesced sweeps
+// over the stored arrays, vector entries gathered through the caches.
+// Products are accumulated in the vector type X (FP64 or FP32); stored
+// FP32/BF16 values are widened exactly before the multiply.  No kernel uses
+// floating-point atomics, so every result is reproducible bit for bit.
+//
+//   CSR  adaptive row blocks: a workgroup streams one block's entries
+//        (fewer than 2*1024, coalesced) into LDS as products, then reduces
+//        each row with a power-of-two group of lanes; a row longer than 1024
+//        entries gets a workgroup of its own.  Vector variants assign W lanes
+//        to each row.
+//   DIA  one thread per row sweeps the diagonals; the diagonal-major layout
+//        makes every value load and every x load contiguous across a wave.
+//   ELL  one thread per row sweeps the K slots (column-major, coalesced).
+//   COO  each wave owns a tile of 64*E consecutive entries (E per lane); rows
+//        are combined with a segmented scan across lanes; rows cut by a tile
+//        boundary are finished by a second pass that adds the per-tile
+//        partials in tile order.
+//   HYB  ELL part writes y, then the COO part adds its rows.
+//   HDC  DIA part writes y, then the CSR part adds its rows.
+#include "core.hpp"
+
+namespace dsm {
+
+constexpr int SB = 256;       // threads per workgroup
+constexpr int RB_T = 1024;    // must match the row-block builder
+constexpr int COO_E = 4;      // entries per lane in the COO kernel
+constexpr int COO_TE = WAVE * COO_E;
+
+template <class X>
+__device__ __forceinline__ void store_y(X *y, i64 i, X v, bool acc) {
+    y[i] = acc ? y[i] + v : v;
+}
+
+// ---------------------------------------------------------------- CSR
+template <class V, class X, bool ACC, bool XCD>
+__global__ void __launch_bounds__(SB) k_csr_adaptive(const i32 *__restrict__ blocks, const i32 *__restrict__ rp,
+                                                     const i32 *__restrict__ col, const V *__restrict__ val,
+                                                     const X *__restrict__ x, X *__restrict__ y) {
+    __shared__ X prod[2 * RB_T];
+    __shared__ X red[SB / WAVE];
+    const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int tid = threadIdx.x;
+    const i64 r0 = blocks[b], r1 = blocks[b + 1];
+    const i64 e0 = rp[r0], e1 = rp[r1];
+    if (r1 - r0 == 1 && e1 - e0 > RB_T) {  // one long row: whole workgroup
+        X s = 0;
+        for (i64 e = e0 + tid; e < e1; e += SB) s += widen<X>(val[e]) * x[col[e]];
+        s = block_sum(s, red);
+        if (tid == 0) store_y(y, r0, s, ACC);
+        return;
+    }
+    for (i64 e = e0 + tid; e < e1; e += SB) prod[e - e0] = widen<X>(val[e]) * x[col[e]];
+    __syncthreads();
+    const int nr = (int)(r1 - r0);
+    const int avg = (int)((e1 - e0 + nr - 1) / nr);
+    int L = 1;
+    while (L < WAVE && 2 * L * nr <= SB && L < avg) L <<= 1;
+    const int rl = tid / L, lane = tid % L;
+    X s = 0;
+    if (rl < nr) {
+        const int a = (int)(rp[r0 + rl] - e0), c = (int)(rp[r0 + rl + 1] - e0);
+        for (int k = a + lane; k < c; k += L) s += prod[k];
+    }
+    for (int off = L >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, WAVE);
+    if (rl < nr && lane == 0) store_y(y, r0 + rl, s, ACC);
+}
+
+template <class V, class X, int W, bool ACC>
+__global__ void __launch_bounds__(SB) k_csr_vector(i64 nrows, const i32 *__restrict__ rp, const i32 *__restrict__ col,
+                                                   const V *__restrict__ val, const X *__restrict__ x,
+                                                   X *__restrict__ y) {
+    const i64 row = ((i64)blockIdx.x * SB + threadIdx.x) / W;
+    const int lane = threadIdx.x % W;
+    X s = 0;
+    if (row < nrows) {
+        const i64 a = rp[row], c = rp[row + 1];
+        for (i64 e = a + lane; e < c; e += W) s += widen<X>(val[e]) * x[col[e]];
+    }
+    s = group_sum<W>(s);
+    if (row < nrows && lane == 0) store_y(y, row, s, ACC);
+}
+
+// ---------------------------------------------------------------- DIA
+template <class V, class X, bool ACC, bool XCD>
+__global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, const i32 *__restrict__ offs,
+                                            const V *__restrict__ dval, i64 pitch, const X *__restrict__ x,
+                                            X *__restrict__ y) {
+    const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const i64 i = (i64)b * SB + threadIdx.x;
+    if (i >= nrows) return;
+    X s = 0;
+#pragma unroll 3
+    for (i64 k = 0; k < ndiag; k++) {
+        const i64 j = i + offs[k];
+        if (j >= 0 && j < ncols) s += widen<X>(dval[k * pitch + i]) * x[j];
+    }
+    store_y(y, i, s, ACC);
+}
+
+// ---------------------------------------------------------------- ELL
+template <class V, class X, bool ACC, bool XCD>
+__global__ void __launch_bounds__(SB) k_ell(i64 nrows, i64 K, i64 pitch, const i32 *__restrict__ ecol,
+                                            const V *__restrict__ evl, const X *__restrict__ x, X *__restrict__ y) {
+    const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const i64 i = (i64)b * SB + threadIdx.x;
+    if (i >= nrows) return;
+    X s = 0;
+#pragma unroll 3
+    for (i64 k = 0; k < K; k++) {
+        const i32 c = ecol[k * pitch + i];
+        if (c >= 0) s += widen<X>(evl[k * pitch + i]) * x[c];
+    }
+    store_y(y, i, s, ACC);
+}
+
+// ---------------------------------------------------------------- COO
+// Tile = one wave's 64*E consecutive entries.  Per tile the kernel records
+// head = sum of the tile's entries of its first row, tail = sum of the
+// entries of its last row.  A row is written here when it both starts and
+// ends inside the tile; a row that starts in this tile and runs on is
+// written by k_coo_fixup; a row that started in an earlier tile only
+// contributes its head.  Empty rows are zeroed by the lane that holds the
+// entry following the gap (non-accumulating mode).
+template <class V, class X, int E, bool ACC>
+__global__ void __launch_bounds__(SB) k_coo_tiles(i64 nnz, i64 nrows, const i32 *__restrict__ row,
+                                                  const i32 *__restrict__ col, const V *__restrict__ val,
+                                                  const X *__restrict__ x, X *__restrict__ y,
+                                                  X *__restrict__ head_val, X *__restrict__ tail_val) {
+    constexpr i32 SENT = INT32_MAX;
+    constexpr i64 TE = (i64)WAVE * E;
+    const int lane = threadIdx.x % WAVE;
+    const i64 tile = (i64)blockIdx.x * (SB / WAVE) + threadIdx.x / WAVE;
+    const i64 t0 = tile * TE;
+    if (t0 >= nnz) return;  // uniform per wave
+    const i64 t1 = min(t0 + TE, nnz);
+    const i64 base = t0 + (i64)lane * E;
+    const int cnt = (int)max((i64)0, min((i64)E, t1 - base));
+
+    i32 r[E];
+    X p[E];
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+        if (k < cnt) {
+            r[k] = row[base + k];
+            p[k] = widen<X>(val[base + k]) * x[col[base + k]];
+        } else {
+            r[k] = SENT;
+            p[k] = 0;
+        }
+    }
+    const i32 fr = cnt > 0 ? r[0] : SENT;
+    const i32 lr = cnt > 0 ? r[cnt - 1] : SENT;
+
+    // tile-level facts (uniform in the wave)
+    const i32 first_row = row[t0];
+    const bool head_before = t0 > 0 && row[t0 - 1] == first_row;
+    const i32 next_tile_row = t1 < nnz ? row[t1] : SENT;
+
+    // empty rows before this lane's first entry / after the last entry
+    if (!ACC && cnt > 0) {
+        const i64 prev = base > 0 ? (i64)row[base - 1] : -1;
+        for (i64 g = prev + 1; g < fr; g++) y[g] = 0;
+        if (base + cnt == nnz)
+            for (i64 g = (i64)lr + 1; g < nrows; g++) y[g] = 0;
+    }
+
+    // lane-local pass: interior rows are complete here
+    X fsum = 0, cur = 0;
+    bool first_done = false;
+    i32 cr = fr;
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+        if (k >= cnt) break;
+        if (r[k] != cr) {
+            if (!first_done) {
+                fsum = cur;
+                first_done = true;
+            } else {
+                store_y(y, cr, cur, ACC);
+            }
+            if (!ACC)
+                for (i64 g = (i64)cr + 1; g < r[k]; g++) y[g] = 0;
+            cr = r[k];
+            cur = 0;
+        }
+        cur += p[k];
+    }
+    const X lsum = cur;
+    if (!first_done) fsum = cur;
+
+    // segmented inclusive scan of the last-row sums across lanes
+    i32 lr_prev = __shfl_up(lr, 1, WAVE);
+    const int head_flag = (lane == 0 || !(fr == lr && lr_prev == fr)) ? 1 : 0;
+    X T = lsum;
+    int h = head_flag;
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+        X tv = __shfl_up(T, off, WAVE);
+        int th = __shfl_up(h, off, WAVE);
+        if (lane >= off && !h) {
+            T += tv;
+            h = th;
+        }
+    }
+    const X T_prev = __shfl_up(T, 1, WAVE);
+    i32 fr_next = __shfl_down(fr, 1, WAVE);
+    if (lane == WAVE - 1) fr_next = next_tile_row;
+    if (cnt == 0) return;
+
+    // first row of the lane when it ends inside the lane
+    if (fr != lr) {
+        const X w = fsum + ((lane > 0 && lr_prev == fr) ? T_prev : (X)0);
+        if (fr == first_row && head_before) head_val[tile] = w;
+        else store_y(y, fr, w, ACC);
+    }
+    // last row of the lane
+    const bool ends_here = fr_next != lr;
+    const bool lr_started_before = lr == first_row && head_before;
+    if (ends_here) {
+        if (lr_started_before) head_val[tile] = T;
+        else store_y(y, lr, T, ACC);
+    }
+    if (base + cnt == t1) {
+        // the wave's last real lane records the tile tail; a tile holding a
+        // single row that runs on from earlier tiles also records it as head
+        tail_val[tile] = T;
+        if (!ends_here && lr_started_before) head_val[tile] = T;
+    }
+}
+
+// Rows that cross tile boundaries: the tile where such a row starts adds its
+// tail to the heads of the following tiles, in tile order.
+template <class X, int E, bool ACC>
+__global__ void k_coo_fixup(i64 nnz, i64 ntiles, const i32 *__restrict__ row, const X *__restrict__ head_val,
+                            const X *__restrict__ tail_val, X *__restrict__ y) {
+    constexpr i64 TE = (i64)WAVE * E;
+    const i64 u = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= ntiles) return;
+    const i64 t0 = u * TE, t1 = min(t0 + TE, nnz);
+    const i32 last = row[t1 - 1];
+    const bool starts_here = row[t0] != last || t0 == 0 || row[t0 - 1] != last;
+    const bool continues = t1 < nnz && row[t1] == last;
+    if (!starts_here || !continues) return;
+    X total = tail_val[u];
+    for (i64 v = u + 1; v < ntiles; v++) {
+        total += head_val[v];
+        const i64 v1 = min((v + 1) * TE, nnz);
+        if (!(v1 < nnz && row[v1] == last)) break;
+    }
+    store_y(y, last, total, ACC);
+}
+
+template <class X>
+__global__ void k_fill(i64 n, X *y, X v) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = v;
+}
+
+// ================================================================ host dispatch
+template <class V, class X>
+static void coo_launch(dsm_matrix m, i64 nnz, const i32 *row, const i32 *col, const V *val, const X *x, X *y,
+                       bool acc, hipStream_t s) {
+    const i64 n = m->nrows;
+    if (nnz == 0) {
+        if (!acc && n > 0) hipLaunchKernelGGL(k_fill<X>, dim3(grid_for(n, SB)), dim3(SB), 0, s, n, y, (X)0);
+        return;
+    }
+    const i64 ntiles = (nnz + COO_TE - 1) / COO_TE;
+    X *scratch = (X *)ws_get(m->ctx, m->ws, sizeof(X) * (size_t)(2 * ntiles));
+    X *head = scratch, *tail = scratch + ntiles;
+    const unsigned g = grid_for(ntiles, SB / WAVE);
+    if (acc) {
+        hipLaunchKernelGGL((k_coo_tiles<V, X, COO_E, true>), dim3(g), dim3(SB), 0, s, nnz, n, row, col, val, x, y,
+                           head, tail);
+        hipLaunchKernelGGL((k_coo_fixup<X, COO_E, true>), dim3(grid_for(ntiles, SB)), dim3(SB), 0, s, nnz, ntiles,
+                           row, head, tail, y);
+    } else {
+        hipLaunchKernelGGL((k_coo_tiles<V, X, COO_E, false>), dim3(g), dim3(SB), 0, s, nnz, n, row, col, val, x, y,
+                           head, tail);
+        hipLaunchKernelGGL((k_coo_fixup<X, COO_E, false>), dim3(grid_for(ntiles, SB)), dim3(SB), 0, s, nnz, ntiles,
+                           row, head, tail, y);
+    }
+}
+
+template <class V, class X, bool ACC>
+static void csr_launch(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s) {
+    const i64 n = m->nrows;
+    if (n == 0) return;
+    const V *val = (const V *)P.val;
+    if (variant == 0 || variant >= 7) {
+        if (P.nrblocks == 0) return;
+        if (variant == 0)
+            hipLaunchKernelGGL((k_csr_adaptive<V, X, ACC, true>), dim3((unsigned)P.nrblocks), dim3(SB), 0, s,
+                               P.rblocks, P.rp, P.col, val, x, y);
+        else
+            hipLaunchKernelGGL((k_csr_adaptive<V, X, ACC, false>), dim3((unsigned)P.nrblocks), dim3(SB), 0, s,
+                               P.rblocks, P.rp, P.col, val, x, y);
+        return;
+    }
+    const int W = 1 << variant;  // 2 .. 64
+    const unsigned g = grid_for(n * W, SB);
+#define VEC(WW) hipLaunchKernelGGL((k_csr_vector<V, X, WW, ACC>), dim3(g), dim3(SB), 0, s, n, P.rp, P.col, val, x, y)
+    switch (W) {
+    case 2: VEC(2); break;
+    case 4: VEC(4); break;
+    case 8: VEC(8); break;
+    case 16: VEC(16); break;
+    case 32: VEC(32); break;
+    default: VEC(64); break;
+    }
+#undef VEC
+}
+
+template <class V, class X>
+static void spmv_typed(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s) {
+    const i64 n = m->nrows, nc = m->ncols;
+    const unsigned g = grid_for(n, SB);
+    const bool xcd = variant != 1;
+    switch (P.fmt) {
+    case DSM_CSR:
+        csr_launch<V, X, false>(m, P, x, y, variant, s);
+        break;
+    case DSM_COO:
+        coo_launch<V, X>(m, P.coo_nnz, P.crow, P.ccol, (const V *)P.cval, x, y, false, s);
+        break;
+    case DSM_DIA:
+    case DSM_HDC:
+        if (n > 0) {
+            if (xcd)
+                hipLaunchKernelGGL((k_dia<V, X, false, true>), dim3(g), dim3(SB), 0, s, n, nc, P.ndiag, P.offs,
+                                   (const V *)P.dval, P.pitch, x, y);
+            else
+                hipLaunchKernelGGL((k_dia<V, X, false, false>), dim3(g), dim3(SB), 0, s, n, nc, P.ndiag, P.offs,
+                                   (const V *)P.dval, P.pitch, x, y);
+        }
+        if (P.fmt == DSM_HDC && P.csr_nnz > 0) csr_launch<V, X, true>(m, P, x, y, 0, s);
+        break;
+    case DSM_ELL:
+    case DSM_HYB:
+        if (n > 0) {
+            if (xcd)
+                hipLaunchKernelGGL((k_ell<V, X, false, true>), dim3(g), dim3(SB), 0, s, n, P.K, P.pitch, P.ecol,
+                                   (const V *)P.evl, x, y);
+            else
+                hipLaunchKernelGGL((k_ell<V, X, false, false>), dim3(g), dim3(SB), 0, s, n, P.K, P.pitch, P.ecol,
+                                   (const V *)P.evl, x, y);
+        }
+        if (P.fmt == DSM_HYB && P.coo_nnz > 0)
+            coo_launch<V, X>(m, P.coo_nnz, P.crow, P.ccol, (const V *)P.cval, x, y, true, s);
+        break;
+    default:
+        fail(DSM_E_INVALID, "spmv: unknown format");
+    }
+    DSM_HIP(hipGetLastError());
+}
+
+void spmv(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant, hipStream_t s) {
+    DSM_CHECK(vdt == DSM_F64 || vdt == DSM_F32, DSM_E_UNSUPPORTED, "spmv: vectors must be F64 or F32");
+    if (vdt == DSM_F64) {
+        const double *xx = (const double *)x;
+        double *yy = (double *)y;
+        switch (P.vdt) {
+        case DSM_F64: spmv_typed<double, double>(m, P, xx, yy, variant, s); break;
+        case DSM_F32: spmv_typed<float, double>(m, P, xx, yy, variant, s); break;
+        default: spmv_typed<bf16, double>(m, P, xx, yy, variant, s); break;
+        }
+    } else {
+        const float *xx = (const float *)x;
+        float *yy = (float *)y;
+        switch (P.vdt) {
+        case DSM_F64: spmv_typed<double, float>(m, P, xx, yy, variant, s); break;
+        case DSM_F32: spmv_typed<float, float>(m, P, xx, yy, variant, s); break;
+        default: spmv_typed<bf16, float>(m, P, xx, yy, variant, s); break;
+        }
+    }
+}
+
+double spmv_bytes(const dsm_matrix_s *m, const Payload &P, int vec_dtype) {
+    const double v = (double)dtype_size(P.vdt), i = 4.0, X = (double)dtype_size(vec_dtype);
+    const double N = (double)m->nrows, NC = (double)m->ncols;
+    const double xy = NC * X + N * X;
+    switch (P.fmt) {
+    case DSM_COO: return (double)P.coo_nnz * (v + 2 * i) + xy;
+    case DSM_CSR: return (double)P.csr_nnz * (v + i) + (N + 1) * i + xy;
+    case DSM_DIA: return (double)P.ndiag * N * v + (double)P.ndiag * i + xy;
+    case DSM_ELL: return (double)P.K * N * (v + i) + xy;
+    case DSM_HYB: return (double)P.K * N * (v + i) + (double)P.coo_nnz * (v + 2 * i) + xy;
+    case DSM_HDC:
+        return (double)P.ndiag * N * v + (double)P.ndiag * i + (double)P.csr_nnz * (v + i) + (N + 1) * i + xy;
+    }
+    return 0;
+}
+
+}  // namespace dsm

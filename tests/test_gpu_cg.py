@@ -1,0 +1,101 @@
+"""CG parity: iteration count within +-1 of the FP64 oracle, true residual
+<= 1.5 tol (recomputed by the oracle), ||x - x_oracle|| <= 10 kappa tol ||x||,
+special cases and failure statuses."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+import paper_2209_06478_amd as dsm
+from gpu_common import FORMATS, log, make_matrix, problem, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+KAPPA = {5: 10.0, 16: 39.05, 104: 1489.4}
+
+
+def solve(p, fmt, tol=1e-10, **kw):
+    torch, dev = torch_dev()
+    A = make_matrix(p)
+    A.convert(fmt)
+    b = torch.from_numpy(p.b).to(dev)
+    x, res = A.cg(b, tol=tol, **kw)
+    xh = x.cpu().numpy()
+    A.close()
+    return xh, res
+
+
+@pytest.mark.parametrize("fmt", FORMATS)
+def test_cg_hpcg16_every_format(fmt):
+    p = problem("hpcg16")
+    xo, it, rr, st = oracle.cg(p.row_ptr, p.col, p.val, p.b, tol=1e-10)
+    log(f"[cg] hpcg16 {fmt}")
+    x, res = solve(p, fmt)
+    assert res["status"] == "converged"
+    assert abs(res["iters"] - it) <= 1, (res, it)
+    assert oracle.true_relres(p.row_ptr, p.col, p.val, p.b, x) <= 1.5e-10
+    assert np.linalg.norm(x - xo) <= 10 * KAPPA[16] * 1e-10 * np.linalg.norm(xo)
+
+
+def test_cg_hpcg104_dia_and_csr():
+    p = problem("hpcg104")
+    for fmt in ["dia", "csr"]:
+        log(f"[cg] hpcg104 {fmt}")
+        x, res = solve(p, fmt)
+        assert res["status"] == "converged"
+        assert abs(res["iters"] - 167) <= 1, res
+        assert oracle.true_relres(p.row_ptr, p.col, p.val, p.b, x) <= 1.5e-10
+        assert np.linalg.norm(x - 1.0) <= 10 * KAPPA[104] * 1e-10 * np.sqrt(p.nrows)
+
+
+def test_cg_special_cases():
+    torch, dev = torch_dev()
+    for n in (1, 2):
+        x, res = solve(inputs.hpcg27(n), "csr")
+        assert res["status"] == "converged" and res["iters"] == 1
+        assert np.max(np.abs(x - 1)) <= 1e-15
+    p = problem("hpcg5")
+    A = make_matrix(p)
+    x, res = A.cg(torch.zeros(p.nrows, dtype=torch.float64, device=dev))
+    assert res["status"] == "converged" and res["iters"] == 0 and not x.any()
+    x, res = A.cg(torch.from_numpy(p.b).to(dev), maxit=3)
+    assert res["status"] == "not_converged" and res["iters"] == 3
+    xo = np.zeros(p.nrows)
+    for _ in range(1):
+        pass
+    bb = p.b.copy()
+    bb[7] = np.nan
+    x, res = A.cg(torch.from_numpy(bb).to(dev))
+    assert res["status"] == "breakdown"
+    A.close()
+
+
+def test_cg_breakdown_on_negative_definite():
+    torch, dev = torch_dev()
+    n = 50
+    rp = np.arange(n + 1, dtype=np.int32)
+    A = dsm.Matrix.from_csr(dsm.Context(0), n, n, rp, np.arange(n, dtype=np.int32), -np.ones(n))
+    x, res = A.cg(torch.ones(n, dtype=torch.float64, device=dev))
+    assert res["status"] == "breakdown" and res["iters"] == 1
+    A.close()
+
+
+def test_cg_nonzero_initial_guess():
+    torch, dev = torch_dev()
+    p = problem("hpcg16")
+    x0 = inputs.uniform_vector(p.nrows, seed=3)
+    xo, it, rr, st = oracle.cg(p.row_ptr, p.col, p.val, p.b, x0=x0, tol=1e-10)
+    A = make_matrix(p)
+    x, res = A.cg(torch.from_numpy(p.b).to(dev), x=torch.from_numpy(x0.copy()).to(dev), tol=1e-10)
+    assert abs(res["iters"] - it) <= 1
+    assert oracle.true_relres(p.row_ptr, p.col, p.val, p.b, x.cpu().numpy()) <= 1.5e-10
+    A.close()
+
+
+def test_cg_rejects_rectangular():
+    torch, dev = torch_dev()
+    p = problem("rect_empty")
+    A = make_matrix(p)
+    with pytest.raises(dsm.DsmError):
+        A.cg(torch.ones(p.nrows, dtype=torch.float64, device=dev))
+    A.close()
