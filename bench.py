@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-spmv", action="store_true", help="skip selection/CG (profiling runs)")
     ap.add_argument("--format", default=None, help="force a format instead of selecting")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="after the timed steps, run a device copy of this many MiB `steps` times "
+                         "(calibration kernel of known size for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -150,6 +153,18 @@ def main():
     value = sel_bytes / (ms_per_step * 1e-3) / 1e9
     achieved = sel_bytes / (avg_us * 1e-6) / 1e9
 
+    copy = None
+    if args.copy_mb > 0:
+        nel = args.copy_mb * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        cus = event_times_us(torch, lambda: dst.copy_(src), args.steps)
+        copy = {"mib": args.copy_mb, "avg_us": round(float(np.mean(cus)), 3),
+                "gbps": round(2 * nel * 8 / (float(np.mean(cus)) * 1e-6) / 1e9, 1)}
+        del src, dst
+
     # CG solves on the selected format
     cg = None
     if not args.only_spmv and args.cg_solves > 0:
@@ -192,6 +207,7 @@ def main():
                       "bytes": int(csr_bytes)},
         "speedup_vs_fixed_csr": round(csr_avg / avg_us, 3),
         "select": sel,
+        "copy_probe": copy,
         "cg": cg,
         "cpu_baseline": cpu,
     }

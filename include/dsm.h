@@ -219,7 +219,13 @@ typedef struct {
     dsm_dtype value_dtype; /* value type of every candidate                   */
     double max_pad_ratio;  /* as in dsm_convert_opts                          */
     double bytes_prefilter;/* skip candidates moving more than this many times
-                              the bytes of the leanest candidate (default 2)  */
+                              the bytes of the leanest candidate timed so far
+                              (CSR is timed first; default 2)                 */
+    int32_t target;        /* what the timing measures: 0 = device-wide SpMV;
+                              1 = one FP64 CG solve of this matrix inside one
+                              workgroup, the path dsm_cg_solve_batched takes
+                              (candidates CSR/DIA/ELL; for CSR the lanes per
+                              row are tuned too)                              */
 } dsm_select_opts;
 
 void dsm_select_opts_default(dsm_select_opts *o);

@@ -260,10 +260,12 @@ class Matrix:
         return out
 
     def select(self, mask=ALL_FORMATS, warmup=3, reps=20, use_cache=True, tune_variant=True, vec_dtype="f64",
-               value_dtype="f64", max_pad_ratio=16.0, bytes_prefilter=2.0, stream=None):
+               value_dtype="f64", max_pad_ratio=16.0, bytes_prefilter=2.0, target=0, stream=None):
+        """target 0: time device-wide SpMV; 1: time one-workgroup CG solves."""
         o = L.SelectOpts()
         lib().dsm_select_opts_default(C.byref(o))
         o.warmup, o.reps, o.use_cache, o.tune_variant = warmup, reps, int(use_cache), int(tune_variant)
+        o.target = int(target)
         o.vec_dtype, o.value_dtype = _dt(vec_dtype), _dt(value_dtype)
         o.max_pad_ratio, o.bytes_prefilter = max_pad_ratio, bytes_prefilter
         r = L.SelectReport()

@@ -38,7 +38,7 @@ class ExportBufs(C.Structure):
 class SelectOpts(C.Structure):
     _fields_ = [("warmup", C.c_int32), ("reps", C.c_int32), ("use_cache", C.c_int32), ("tune_variant", C.c_int32),
                 ("vec_dtype", C.c_int), ("value_dtype", C.c_int), ("max_pad_ratio", C.c_double),
-                ("bytes_prefilter", C.c_double)]
+                ("bytes_prefilter", C.c_double), ("target", C.c_int32)]
 
 
 class SelectReport(C.Structure):

@@ -202,11 +202,11 @@ struct CgBuffers {
     float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr, *ri32 = nullptr;
 };
 
-static CgBuffers cg_buffers(dsm_matrix m, bool ir) {
+static CgBuffers cg_buffers(dsm_matrix m, bool ir, Workspace &cgws) {
     const size_t n = (size_t)std::max<i64>(m->nrows, 1);
     size_t bytes = 3 * ((n * 8 + 255) & ~(size_t)255) + 8 * 256 + 2 * CGG * 8;
     if (ir) bytes += 5 * ((n * 4 + 255) & ~(size_t)255);
-    char *base = (char *)ws_get(m->ctx, m->cgws, bytes);
+    char *base = (char *)ws_get(m->ctx, cgws, bytes);
     CgBuffers B;
     auto take = [&](size_t sz) {
         char *p = base;
@@ -245,12 +245,13 @@ static unsigned vec_grid(i64 n) { return (unsigned)std::max<i64>(1, std::min<i64
 // Returns the final state (read back).
 template <class X>
 static CgState run_cg(dsm_matrix m, const X *b, X *x, X *r, X *p, X *q, double *part_a, double *part_b,
-                      CgState *st, int vdt, double tol, long long maxit, int check_every, hipStream_t s) {
+                      CgState *st, int vdt, double tol, long long maxit, int check_every, hipStream_t s,
+                      Workspace &spws) {
     const i64 n = m->nrows;
     // grid of the vector kernels is always CGG so every partial slot is written
     const unsigned G = CGG;
     (void)vec_grid;
-    spmv(m, m->P, x, q, vdt, m->variant, s);
+    spmv(m, m->P, x, q, vdt, m->variant, s, &spws);
     hipLaunchKernelGGL((k_cg_init<X>), dim3(G), dim3(CGB), 0, s, n, b, q, r, p, part_a);
     hipLaunchKernelGGL(k_cg_init_state, dim3(1), dim3(CGB), 0, s, part_a, st, tol, maxit);
     DSM_HIP(hipGetLastError());
@@ -258,7 +259,7 @@ static CgState run_cg(dsm_matrix m, const X *b, X *x, X *r, X *p, X *q, double *
     long long enq = 0;
     for (;;) {
         for (int j = 0; j < check_every && enq < maxit; j++, enq++) {
-            spmv(m, m->P, p, q, vdt, m->variant, s);
+            spmv(m, m->P, p, q, vdt, m->variant, s, &spws);
             hipLaunchKernelGGL((k_cg_dot_pq<X>), dim3(G), dim3(CGB), 0, s, n, p, q, part_a, st);
             hipLaunchKernelGGL((k_cg_update_xr<X>), dim3(G), dim3(CGB), 0, s, n, x, r, p, q, part_a, part_b, st);
             hipLaunchKernelGGL((k_cg_update_p<X>), dim3(G), dim3(CGB), 0, s, n, r, p, part_b, st);
@@ -272,9 +273,10 @@ static CgState run_cg(dsm_matrix m, const X *b, X *x, X *r, X *p, X *q, double *
 }
 
 // ||b - A x|| / ||b|| in FP64 on the device (A with its stored values)
-static double true_relres(dsm_matrix m, const double *b, const double *x, CgBuffers &B, hipStream_t s) {
+static double true_relres(dsm_matrix m, const double *b, const double *x, CgBuffers &B, hipStream_t s,
+                          Workspace &spws) {
     const i64 n = m->nrows;
-    spmv(m, m->P, x, B.q, DSM_F64, m->variant, s);
+    spmv(m, m->P, x, B.q, DSM_F64, m->variant, s, &spws);
     hipLaunchKernelGGL(k_residual, dim3(CGG), dim3(CGB), 0, s, n, b, B.q, B.r, B.part_a, B.part_b);
     hipLaunchKernelGGL(k_norms, dim3(1), dim3(CGB), 0, s, B.part_a, B.part_b, B.norms);
     DSM_HIP(hipGetLastError());
@@ -286,7 +288,8 @@ static double true_relres(dsm_matrix m, const double *b, const double *x, CgBuff
 
 static int default_check_every(i64 n) { return n < 100000 ? 32 : 8; }
 
-void cg_solve(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o, dsm_cg_result *res, hipStream_t s) {
+void cg_solve_ws(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o, dsm_cg_result *res, hipStream_t s,
+                 Workspace &cgws, Workspace &spws) {
     DSM_CHECK(m->nrows == m->ncols, DSM_E_UNSUPPORTED, "CG needs a square matrix");
     const i64 n = m->nrows;
     long long maxit = o.maxit > 0 ? o.maxit : std::min<long long>(10 * std::max<i64>(n, 1), 20000);
@@ -296,18 +299,19 @@ void cg_solve(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o, ds
     DSM_CHECK(o.mode == DSM_CG_F64 || o.mode == DSM_CG_IR, DSM_E_INVALID, "unknown CG mode");
     DSM_CHECK(!ir || m->P.vdt != DSM_F64, DSM_E_UNSUPPORTED,
               "iterative refinement needs F32 or BF16 matrix values (convert with value_dtype)");
-    CgBuffers B = cg_buffers(m, ir);
+    CgBuffers B = cg_buffers(m, ir, cgws);
     if (n == 0) {
         R.status = DSM_OK;
         *res = R;
         return;
     }
     if (!ir) {
-        CgState h = run_cg<double>(m, b, x, B.r, B.p, B.q, B.part_a, B.part_b, B.st, DSM_F64, o.tol, maxit, every, s);
+        CgState h = run_cg<double>(m, b, x, B.r, B.p, B.q, B.part_a, B.part_b, B.st, DSM_F64, o.tol, maxit, every, s,
+                                   spws);
         R.iters = h.iters;
         R.relres = h.relres;
         R.status = h.done == 1 ? DSM_OK : h.done == 3 ? DSM_E_BREAKDOWN : DSM_E_NOT_CONVERGED;
-        R.relres_true = true_relres(m, b, x, B, s);
+        R.relres_true = true_relres(m, b, x, B, s, spws);
         *res = R;
         return;
     }
@@ -319,7 +323,7 @@ void cg_solve(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o, ds
     double relres = 1.0;
     for (int outer = 0;; outer++) {
         // r = b - A x in FP64, norms
-        spmv(m, m->P, x, B.q, DSM_F64, m->variant, s);
+        spmv(m, m->P, x, B.q, DSM_F64, m->variant, s, &spws);
         hipLaunchKernelGGL(k_residual, dim3(CGG), dim3(CGB), 0, s, n, b, B.q, B.r, B.part_a, B.part_b);
         hipLaunchKernelGGL(k_norms, dim3(1), dim3(CGB), 0, s, B.part_a, B.part_b, B.norms);
         DSM_HIP(hipGetLastError());
@@ -342,7 +346,7 @@ void cg_solve(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o, ds
         DSM_HIP(hipGetLastError());
         // the scaled residual r32 is the inner right-hand side, d32 the inner iterate
         CgState h = run_cg<float>(m, B.r32, B.d32, B.ri32, B.p32, B.q32, B.part_a, B.part_b, B.st2, DSM_F32,
-                                  inner_tol, std::max<long long>(1, maxit - inner_total), every, s);
+                                  inner_tol, std::max<long long>(1, maxit - inner_total), every, s, spws);
         inner_total += h.iters;
         if (h.done == 3 && h.iters <= 1) {
             status = DSM_E_BREAKDOWN;
@@ -354,7 +358,7 @@ void cg_solve(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o, ds
     R.iters = inner_total;
     R.relres = relres;
     R.status = status;
-    R.relres_true = true_relres(m, b, x, B, s);
+    R.relres_true = true_relres(m, b, x, B, s, spws);
     *res = R;
 }
 
@@ -385,7 +389,7 @@ DSM_API dsm_status dsm_cg_solve(dsm_matrix m, const double *b, double *x, const 
         if (opts) o = *opts;
         DSM_CHECK(o.tol >= 0, DSM_E_INVALID, "negative tolerance");
         hipStream_t s = (hipStream_t)stream;
-        cg_solve(m, b, x, o, &R, s);
+        cg_solve_ws(m, b, x, o, &R, s, m->cgws, m->ws);
         m->last_stream = s;
     });
     if (result) *result = R;

@@ -83,6 +83,7 @@ struct dsm_matrix_s {
     int64_t nrows = 0, ncols = 0, nnz = 0;
     dsm::Payload P;
     int variant = 0;
+    int batch_lanes = 0;  // CSR lanes per row in the one-workgroup solver (0 = by mean row length)
     hipStream_t last_stream = nullptr;
     dsm::Workspace ws;   // SpMV scratch (COO tile carries)
     dsm::Workspace cgws; // CG vectors and scalars
@@ -121,12 +122,33 @@ Payload coo_to_csr_payload(dsm_matrix m, const i32 *row, const i32 *col, const d
 void row_stats(dsm_matrix m, i64 *out, hipStream_t s);
 
 // ---------------------------------------------------------------- spmv.hip
-// y (=|+=) A x for one payload; vector dtype F64 or F32.
+// y = A x for one payload; vector dtype F64 or F32.  `scratch` holds the
+// COO tile partials (the matrix's own workspace when null).
 void spmv(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant,
-          hipStream_t s);
+          hipStream_t s, Workspace *scratch = nullptr);
 // Algorithmic bytes one SpMV must move (x read once, y written once).
 double spmv_bytes(const dsm_matrix_s *m, const Payload &P, int vec_dtype);
 // Number of CSR kernel variants (index 0 = adaptive).
 constexpr int CSR_VARIANTS = 8;
+
+// ---------------------------------------------------------------- cg.hip / batched.hip
+// CG with caller-provided workspaces (vectors/scalars, SpMV scratch).
+void cg_solve_ws(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o, dsm_cg_result *res,
+                 hipStream_t s, Workspace &cgws, Workspace &spws);
+size_t cg_workspace_bytes(i64 n, bool ir);
+// One-workgroup solver: eligibility, per-request device bytes, and timing
+// of one solve of `P` with `lanes` (CSR) for `iters` iterations (us).
+bool batch_eligible(const dsm_matrix_s *m, i64 small_rows);
+size_t batch_request_bytes(i64 n);
+double time_batched_solve(dsm_matrix m, const Payload &P, int lanes, int iters, hipStream_t s);
+struct BatchJob {
+    std::vector<dsm_matrix> mats;
+    std::vector<const double *> b;
+    std::vector<double *> x;
+    std::vector<dsm_cg_opts> opts;
+};
+// Runs one persistent launch for `job` on s and waits for it; fills
+// results[0 .. job.mats.size()).
+void run_batch(dsm_ctx ctx, const BatchJob &job, dsm_cg_result *results, Workspace &arena, hipStream_t s);
 
 }  // namespace dsm

@@ -15,6 +15,8 @@ namespace dsm {
 
 Payload build_format(dsm_matrix m, int fmt, const dsm_convert_opts &o, hipStream_t s);
 
+constexpr int BATCH_TUNE_ITERS = 20;  // CG iterations one batched-solver timing runs
+
 template <class T>
 __global__ void k_fill_value(i64 n, T *y, T v) {
     i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -65,10 +67,17 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
     for (int f = 0; f < DSM_NUM_FORMATS; f++) R.status[f] = DSM_E_UNSUPPORTED;
     const int vec = o.vec_dtype;
     DSM_CHECK(vec == DSM_F64 || vec == DSM_F32, DSM_E_INVALID, "vec_dtype must be F64 or F32");
+    DSM_CHECK(o.target == 0 || o.target == 1, DSM_E_INVALID, "target must be 0 or 1");
     mask &= (1u << DSM_NUM_FORMATS) - 1;
+    if (o.target == 1) {
+        DSM_CHECK(m->nrows == m->ncols, DSM_E_UNSUPPORTED, "the batched solver needs a square matrix");
+        DSM_CHECK(o.value_dtype == DSM_F64, DSM_E_UNSUPPORTED, "the batched solver uses FP64 values");
+        mask &= (1u << DSM_CSR) | (1u << DSM_DIA) | (1u << DSM_ELL);
+    }
     DSM_CHECK(mask != 0, DSM_E_INVALID, "empty candidate mask");
     m->last_stream = s;
-    const std::string key = fingerprint(m, o.value_dtype, vec) + ":m" + std::to_string(mask);
+    const std::string key =
+        fingerprint(m, o.value_dtype, vec) + ":m" + std::to_string(mask) + ":t" + std::to_string(o.target);
 
     dsm_convert_opts co;
     dsm_convert_opts_default(&co);
@@ -89,7 +98,11 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
                 m->P.release(ctx);
                 m->P = np;
             }
-            m->variant = hit.second;
+            if (o.target == 1) {
+                m->batch_lanes = hit.first == DSM_CSR ? hit.second : 0;
+            } else {
+                m->variant = hit.second;
+            }
             R.chosen = hit.first;
             R.chosen_variant = hit.second;
             R.cache_hit = 1;
@@ -162,16 +175,19 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
                 continue;
             }
             min_bytes = min_bytes > 0 ? std::min(min_bytes, bytes) : bytes;
-            // kernel variants of this format
+            // kernel variants of this format (target 1: CSR lanes per row)
             std::vector<int> variants{0};
-            if (o.tune_variant) {
+            if (o.target == 1) {
+                variants = f == DSM_CSR ? std::vector<int>{1, 2, 4, 8, 16, 32} : std::vector<int>{1};
+            } else if (o.tune_variant) {
                 if (f == DSM_CSR) variants = {0, 7, 2, 3, 4, 5, 6};
                 else if (f == DSM_DIA || f == DSM_ELL) variants = {0, 1};
             }
             double tf = 0;
             int vf = 0;
             for (int v : variants) {
-                double t = time_spmv(m, P, v, x, y, vec, o.warmup, o.reps, s);
+                double t = o.target == 1 ? time_batched_solve(m, P, v, BATCH_TUNE_ITERS, s)
+                                         : time_spmv(m, P, v, x, y, vec, o.warmup, o.reps, s);
                 if (v == variants[0] || t < tf) {
                     tf = t;
                     vf = v;
@@ -215,7 +231,12 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
         m->P.release(ctx);
         m->P = best;
     }
-    m->variant = best_v;
+    if (o.target == 1) {
+        m->batch_lanes = best_f == DSM_CSR ? best_v : 0;
+        m->variant = 0;
+    } else {
+        m->variant = best_v;
+    }
     R.chosen = best_f;
     R.chosen_variant = best_v;
     {
@@ -239,6 +260,7 @@ DSM_API void dsm_select_opts_default(dsm_select_opts *o) {
     o->value_dtype = DSM_F64;
     o->max_pad_ratio = 16.0;
     o->bytes_prefilter = 2.0;
+    o->target = 0;
 }
 
 DSM_API dsm_status dsm_select(dsm_matrix m, uint32_t candidate_mask, const dsm_select_opts *opts,

@@ -262,15 +262,15 @@ __global__ void k_fill(i64 n, X *y, X v) {
 // ================================================================ host dispatch
 template <class V, class X>
 static void coo_launch(dsm_matrix m, i64 nnz, const i32 *row, const i32 *col, const V *val, const X *x, X *y,
-                       bool acc, hipStream_t s) {
+                       bool acc, hipStream_t s, Workspace *scratch) {
     const i64 n = m->nrows;
     if (nnz == 0) {
         if (!acc && n > 0) hipLaunchKernelGGL(k_fill<X>, dim3(grid_for(n, SB)), dim3(SB), 0, s, n, y, (X)0);
         return;
     }
     const i64 ntiles = (nnz + COO_TE - 1) / COO_TE;
-    X *scratch = (X *)ws_get(m->ctx, m->ws, sizeof(X) * (size_t)(2 * ntiles));
-    X *head = scratch, *tail = scratch + ntiles;
+    X *part = (X *)ws_get(m->ctx, scratch ? *scratch : m->ws, sizeof(X) * (size_t)(2 * ntiles));
+    X *head = part, *tail = part + ntiles;
     const unsigned g = grid_for(ntiles, SB / WAVE);
     if (acc) {
         hipLaunchKernelGGL((k_coo_tiles<V, X, COO_E, true>), dim3(g), dim3(SB), 0, s, nnz, n, row, col, val, x, y,
@@ -315,7 +315,8 @@ static void csr_launch(dsm_matrix m, const Payload &P, const X *x, X *y, int var
 }
 
 template <class V, class X>
-static void spmv_typed(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s) {
+static void spmv_typed(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s,
+                       Workspace *scratch) {
     const i64 n = m->nrows, nc = m->ncols;
     const unsigned g = grid_for(n, SB);
     const bool xcd = variant != 1;
@@ -324,7 +325,7 @@ static void spmv_typed(dsm_matrix m, const Payload &P, const X *x, X *y, int var
         csr_launch<V, X, false>(m, P, x, y, variant, s);
         break;
     case DSM_COO:
-        coo_launch<V, X>(m, P.coo_nnz, P.crow, P.ccol, (const V *)P.cval, x, y, false, s);
+        coo_launch<V, X>(m, P.coo_nnz, P.crow, P.ccol, (const V *)P.cval, x, y, false, s, scratch);
         break;
     case DSM_DIA:
     case DSM_HDC:
@@ -349,7 +350,7 @@ static void spmv_typed(dsm_matrix m, const Payload &P, const X *x, X *y, int var
                                    (const V *)P.evl, x, y);
         }
         if (P.fmt == DSM_HYB && P.coo_nnz > 0)
-            coo_launch<V, X>(m, P.coo_nnz, P.crow, P.ccol, (const V *)P.cval, x, y, true, s);
+            coo_launch<V, X>(m, P.coo_nnz, P.crow, P.ccol, (const V *)P.cval, x, y, true, s, scratch);
         break;
     default:
         fail(DSM_E_INVALID, "spmv: unknown format");
@@ -357,23 +358,24 @@ static void spmv_typed(dsm_matrix m, const Payload &P, const X *x, X *y, int var
     DSM_HIP(hipGetLastError());
 }
 
-void spmv(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant, hipStream_t s) {
+void spmv(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant, hipStream_t s,
+          Workspace *scratch) {
     DSM_CHECK(vdt == DSM_F64 || vdt == DSM_F32, DSM_E_UNSUPPORTED, "spmv: vectors must be F64 or F32");
     if (vdt == DSM_F64) {
         const double *xx = (const double *)x;
         double *yy = (double *)y;
         switch (P.vdt) {
-        case DSM_F64: spmv_typed<double, double>(m, P, xx, yy, variant, s); break;
-        case DSM_F32: spmv_typed<float, double>(m, P, xx, yy, variant, s); break;
-        default: spmv_typed<bf16, double>(m, P, xx, yy, variant, s); break;
+        case DSM_F64: spmv_typed<double, double>(m, P, xx, yy, variant, s, scratch); break;
+        case DSM_F32: spmv_typed<float, double>(m, P, xx, yy, variant, s, scratch); break;
+        default: spmv_typed<bf16, double>(m, P, xx, yy, variant, s, scratch); break;
         }
     } else {
         const float *xx = (const float *)x;
         float *yy = (float *)y;
         switch (P.vdt) {
-        case DSM_F64: spmv_typed<double, float>(m, P, xx, yy, variant, s); break;
-        case DSM_F32: spmv_typed<float, float>(m, P, xx, yy, variant, s); break;
-        default: spmv_typed<bf16, float>(m, P, xx, yy, variant, s); break;
+        case DSM_F64: spmv_typed<double, float>(m, P, xx, yy, variant, s, scratch); break;
+        case DSM_F32: spmv_typed<float, float>(m, P, xx, yy, variant, s, scratch); break;
+        default: spmv_typed<bf16, float>(m, P, xx, yy, variant, s, scratch); break;
         }
     }
 }

@@ -1,0 +1,96 @@
+"""Format selection: the chosen format is feasible and, re-timed against
+fresh conversions of every candidate, within 5% of the fastest median
+(ties/jitter slack of 1.5 us); repeated structures hit the cache; the
+one-workgroup target picks among CSR/DIA/ELL and tunes CSR lanes."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+import paper_2209_06478_amd as dsm
+from gpu_common import log, make_matrix, problem, row_scaled_err, torch_dev, x_for
+
+pytestmark = pytest.mark.gpu
+
+
+def median_us(A, x, y, reps=30):
+    torch, _ = torch_dev()
+    for _ in range(3):
+        A.spmv(x, out=y)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        A.spmv(x, out=y)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) * 1e3)
+    return float(np.median(ts))
+
+
+@pytest.mark.parametrize("name", ["hpcg16", "hpcg104", "zipf50k", "banded20k"])
+def test_select_is_near_best(name):
+    torch, dev = torch_dev()
+    p = problem(name)
+    A = make_matrix(p)
+    rep = A.select(use_cache=False)
+    log(f"[select] {name}: chose {rep['chosen']} v{rep['chosen_variant']} medians {rep['median_us']}")
+    assert rep["status"][rep["chosen"]] == 0
+    x = torch.from_numpy(x_for(p)).to(dev)
+    y = torch.empty(p.nrows, dtype=torch.float64, device=dev)
+    chosen_t = median_us(A, x, y)
+    yref, scale = oracle.spmv_csr_ref(p.row_ptr, p.col, p.val, x_for(p))
+    assert row_scaled_err(A.spmv(x).cpu().numpy(), yref, scale) <= 1e-14
+    best = chosen_t
+    for f, st in rep["status"].items():
+        if st != 0 or f == rep["chosen"]:
+            continue
+        B = make_matrix(p)
+        B.convert(f)
+        if f in ("dia", "ell", "csr"):
+            ts = []
+            for v in ([0, 7, 2, 3, 4, 5, 6] if f == "csr" else [0, 1]):
+                B.variant = v
+                ts.append(median_us(B, x, y))
+            t = min(ts)
+        else:
+            t = median_us(B, x, y)
+        best = min(best, t)
+        B.close()
+    log(f"[select] {name}: chosen {chosen_t:.1f} us, best re-timed {best:.1f} us")
+    assert chosen_t <= 1.05 * best + 1.5
+    A.close()
+
+
+def test_select_cache_hit_on_same_structure():
+    p = problem("hpcg16")
+    A = make_matrix(p)
+    r1 = A.select(use_cache=True)
+    B = dsm.Matrix.from_csr(A.ctx, p.nrows, p.ncols, p.row_ptr, p.col, p.val * 2.0)
+    r2 = B.select(use_cache=True)
+    assert r2["cache_hit"] and r2["chosen"] == r1["chosen"] and B.format == r1["chosen"]
+    A.close()
+    B.close()
+
+
+def test_select_prunes_infeasible():
+    p = problem("zipf50k")
+    A = make_matrix(p)
+    rep = A.select(use_cache=False)
+    assert rep["status"]["dia"] == dsm.L.E_INFEASIBLE and rep["status"]["ell"] == dsm.L.E_INFEASIBLE
+    assert rep["chosen"] in ("csr", "hyb", "coo", "hdc")
+    A.close()
+
+
+def test_select_batched_target():
+    torch, dev = torch_dev()
+    p = problem("hpcg16")
+    A = make_matrix(p)
+    rep = A.select(target=1, use_cache=False)
+    log(f"[select-batched] chose {rep['chosen']} lanes {rep['chosen_variant']} times {rep['median_us']}")
+    assert rep["chosen"] in ("csr", "dia", "ell")
+    assert all(rep["status"][f] == dsm.L.E_UNSUPPORTED for f in ("coo", "hyb", "hdc"))
+    res = dsm.cg_batched([A], [torch.from_numpy(p.b).to(dev)], [torch.zeros(p.nrows, dtype=torch.float64,
+                                                                          device=dev)])[0]
+    assert res["status"] == "converged" and abs(res["iters"] - 27) <= 1
+    A.close()
