@@ -20,6 +20,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy of known size; keyed by
+# (workload, format, kernel variant).  Source: profiles/dia_spmv_hpcg104.md.
+# An entry is removed when its kernel changes.
+PROFILED_TRAFFIC = {
+    ("hpcg27_104", "dia", 0): 262312051,
+}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -64,6 +72,141 @@ def cpu_baseline(p, budget_s=12.0):
                       f"{ncg / (time.perf_counter() - t1):.1f} solves/s single-threaded"}
 
 
+def ir_bench(dsm, ctx, torch, dev, n=128):
+    """FP64 plain CG vs iterative refinement with FP32/BF16 values on HPCG n^3
+    and ANISO7 n^3 (z-coupling x100), all to 1e-10 relative residual."""
+    import numpy as np
+    import inputs
+    out = {}
+    for name, gen in (("hpcg27", inputs.hpcg27), ("aniso7", inputs.aniso7)):
+        log(f"[bench] IR-CG on {name}_{n}")
+        p = gen(n)
+        b = torch.from_numpy(p.b).to(dev)
+        row = {}
+        for label, fmt, vdt, mode in (("f64_csr", "csr", "f64", "f64"), ("f64_dia", "dia", "f64", "f64"),
+                                      ("ir_f32_dia", "dia", "f32", "ir"), ("ir_bf16_dia", "dia", "bf16", "ir")):
+            A = dsm.Matrix.from_csr(ctx, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
+            A.convert(fmt, value_dtype=vdt)
+            ts, res, x = [], None, None
+            for rep in range(3):
+                x0 = torch.zeros(p.nrows, dtype=torch.float64, device=dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, res = A.cg(b, x=x0, tol=1e-10, mode=mode)
+                ts.append(time.perf_counter() - t0)
+            row[label] = {"ms": round(min(ts) * 1e3, 3), "iters": res["iters"], "outer": res["outer_iters"],
+                          "relres_true": res["relres_true"], "status": res["status"],
+                          "err_vs_ones": float(torch.linalg.norm(x - 1.0) / np.sqrt(p.nrows))}
+            A.close()
+        base = row["f64_csr"]["ms"]
+        for k in row:
+            row[k]["speedup_vs_f64_csr"] = round(base / row[k]["ms"], 3)
+        out[f"{name}_{n}"] = row
+    return out
+
+
+def serving_bench(dsm, ctx, torch, dev, nreq=10000, load=0.8, seed=0x5E4E):
+    """Poisson stream of CG solves (tol 1e-8) over a pool of resident
+    matrices: 27-point stencils 8^3..96^3 and banded SPD 1k..200k rows."""
+    import threading
+    import numpy as np
+    import inputs
+    log("[bench] serving: building the matrix pool")
+    pool, keys = [], {}
+    for n in range(8, 97, 8):
+        keys[("s", n)] = len(pool)
+        pool.append(inputs.hpcg27(n))
+    lo, hi = np.log(1e3), np.log(2e5)
+    u = inputs.uniform(seed, 41, np.arange(48, dtype=np.uint64))
+    h = inputs.uniform(seed, 42, np.arange(48, dtype=np.uint64))
+    bidx = []
+    for k in range(24):
+        N = int(np.exp(lo + u[k] * (hi - lo)))
+        hbw = 1 + int(h[k] * 64)
+        bidx.append(len(pool))
+        pool.append(inputs.banded_spd(N, hbw, seed=seed + k))
+    mats, bvec = [], []
+    for p in pool:
+        A = dsm.Matrix.from_csr(ctx, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
+        if p.nrows <= 40000:
+            A.select(target=1)
+        else:
+            A.select()
+        mats.append(A)
+        bvec.append(torch.from_numpy(p.b).to(dev))
+    reqs = inputs.serving_stream(nreq, seed=seed)
+    order = []
+    for r in reqs:
+        if r["kind"] == "hpcg27":
+            n = min(96, max(8, int(round(r["n"] / 8.0)) * 8))
+            order.append(keys[("s", n)])
+        else:
+            order.append(bidx[r["id"] % len(bidx)])
+    torch.cuda.synchronize()
+
+    def run(arrivals):
+        srv = dsm.Server(ctx, slots=128, streams=4, batch_max=256)
+        tickets = [None] * len(order)
+        xs = [None] * len(order)
+        t0 = srv.now()
+
+        def submitter():
+            for i, k in enumerate(order):
+                if arrivals is not None:
+                    dt = t0 + arrivals[i] - srv.now()
+                    if dt > 0:
+                        time.sleep(dt)
+                xs[i] = torch.zeros(pool[k].nrows, dtype=torch.float64, device=dev)
+                torch.cuda.current_stream().synchronize()
+                tickets[i] = srv.submit(mats[k], bvec[k], xs[i], tol=1e-8)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        lat, iters, bad = [], 0, 0
+        for i in range(len(order)):
+            while tickets[i] is None:
+                time.sleep(0.0002)
+            res, ts = srv.wait(tickets[i])
+            lat.append(ts["finish"] - ts["arrival"])
+            iters += res["iters"]
+            bad += res["status"] != "converged"
+            xs[i] = None
+        th.join()
+        wall = srv.now() - t0
+        srv.close()
+        lat = np.array(lat) * 1e3
+        return {"requests": len(order), "wall_s": round(wall, 3), "solves_per_s": round(len(order) / wall, 1),
+                "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "mean_iters": round(iters / len(order), 1), "not_converged": bad}
+
+    log(f"[bench] serving: saturation run ({nreq} requests at once)")
+    sat = run(None)
+    rate = sat["solves_per_s"] * load
+    gaps = -np.log(1.0 - inputs.uniform(seed, 43, np.arange(nreq, dtype=np.uint64))) / rate
+    log(f"[bench] serving: Poisson run at {load} x saturation ({rate:.0f}/s)")
+    open_loop = run(np.cumsum(gaps))
+    # baseline: one request at a time, FP64 CSR device-wide CG, on a sample
+    log("[bench] serving: sequential FP64 CSR baseline")
+    csr = {}
+    for k in set(order[:300]):
+        p = pool[k]
+        csr[k] = dsm.Matrix.from_csr(ctx, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
+    t0 = time.perf_counter()
+    lat = []
+    for k in order[:300]:
+        x0 = torch.zeros(pool[k].nrows, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        csr[k].cg(bvec[k], x=x0, tol=1e-8)
+        lat.append((time.perf_counter() - t1) * 1e3)
+    seq = {"requests": 300, "solves_per_s": round(300 / (time.perf_counter() - t0), 1),
+           "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+    for A in list(csr.values()) + mats:
+        A.close()
+    return {"pool": len(pool), "tol": 1e-8, "saturation": sat, "poisson": dict(open_loop, load=load),
+            "sequential_fp64_csr": seq}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,7 +216,11 @@ def main():
     ap.add_argument("--cg-solves", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-spmv", action="store_true", help="skip selection/CG (profiling runs)")
+    ap.add_argument("--no-ir", action="store_true", help="skip the mixed-precision CG leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--format", default=None, help="force a format instead of selecting")
+    ap.add_argument("--variant", type=int, default=None, help="kernel variant with --format")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, run a device copy of this many MiB `steps` times "
                          "(calibration kernel of known size for the HBM byte counters)")
@@ -117,6 +264,8 @@ def main():
     sel = None
     if args.format:
         A.convert(args.format)
+        if args.variant is not None:
+            A.variant = args.variant
     elif not args.only_spmv:
         log("[bench] selecting")
         t0 = time.perf_counter()
@@ -184,6 +333,9 @@ def main():
               "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
               "ms_per_iter": round(float(lat.mean()) / max(res["iters"], 1), 4)}
 
+    ir = None if (args.only_spmv or args.no_ir) else ir_bench(dsm, ctx, torch, dev)
+    serve = None if (args.only_spmv or args.no_serve) else serving_bench(dsm, ctx, torch, dev,
+                                                                          nreq=args.serve_requests)
     cpu = None if args.no_cpu else cpu_baseline(p)
     out = {
         "metric": "SpMV GB/s vs HBM peak (selected vs fixed CSR); CG solves/s + p99 latency",
@@ -201,7 +353,8 @@ def main():
         "config": {"workload": f"hpcg27_{args.n}", "nrows": N, "nnz": nnz, "format": fmt,
                    "variant": A.variant, "value_dtype": "f64", "vector_dtype": "f64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": PROFILED_TRAFFIC.get((f"hpcg27_{args.n}", fmt, A.variant)),
                      "kernel_avg_us": round(avg_us, 3), "algorithmic_bytes": int(sel_bytes)},
         "fixed_csr": {"gbps": round(csr_bytes / (csr_avg * 1e-6) / 1e9, 2), "avg_us": round(csr_avg, 3),
                       "bytes": int(csr_bytes)},
@@ -209,6 +362,8 @@ def main():
         "select": sel,
         "copy_probe": copy,
         "cg": cg,
+        "ir_cg": ir,
+        "serving": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -41,8 +41,15 @@ void dev_free(dsm_ctx ctx, void *p, size_t bytes) {
     ctx->in_use -= bytes == 0 ? 16 : bytes;
 }
 
+static void drop_graph(Workspace &w) {
+    if (w.graph) (void)hipGraphExecDestroy((hipGraphExec_t)w.graph);
+    w.graph = nullptr;
+    w.graph_key.clear();
+}
+
 void *ws_get(dsm_ctx ctx, Workspace &w, size_t bytes) {
     if (w.bytes >= bytes && w.p) return w.p;
+    drop_graph(w);
     if (w.p) {
         DSM_HIP(hipDeviceSynchronize());
         dev_free(ctx, w.p, w.bytes);
@@ -55,6 +62,9 @@ void *ws_get(dsm_ctx ctx, Workspace &w, size_t bytes) {
 }
 
 void ws_release(dsm_ctx ctx, Workspace &w) {
+    drop_graph(w);
+    if (w.stream) (void)hipStreamDestroy(w.stream);
+    w.stream = nullptr;
     if (w.p) dev_free(ctx, w.p, w.bytes);
     w.p = nullptr;
     w.bytes = 0;
@@ -396,7 +406,8 @@ DSM_API dsm_status dsm_spmv(dsm_matrix m, const void *x, void *y, dsm_dtype vec_
 DSM_API dsm_status dsm_set_variant(dsm_matrix m, int32_t variant) {
     return guard([&] {
         check_matrix(m);
-        int maxv = m->P.fmt == DSM_CSR ? CSR_VARIANTS : 2;
+        const int f = m->P.fmt;
+        int maxv = f == DSM_CSR ? CSR_VARIANTS : (f == DSM_COO ? 1 : SWEEP_VARIANT_COUNT);
         DSM_CHECK(variant >= 0 && variant < maxv, DSM_E_INVALID, "no such kernel variant for this format");
         m->variant = variant;
     });

@@ -394,7 +394,7 @@ DSM_API dsm_status dsm_cg_solve_batched(int32_t count, const dsm_matrix *mats, c
                     }
                 });
                 try {
-                    for (int k : large) cg_solve_ws(mats[k], b[k], x[k], opts[k], &results[k], side, cgws, spws);
+                    for (int k : large) cg_solve_ws(mats[k], b[k], x[k], opts[k], &results[k], side, cgws, spws, false);
                 } catch (...) {
                     th.join();
                     throw;
@@ -402,7 +402,7 @@ DSM_API dsm_status dsm_cg_solve_batched(int32_t count, const dsm_matrix *mats, c
                 th.join();
                 if (err) std::rethrow_exception(err);
             } else {
-                for (int k : large) cg_solve_ws(mats[k], b[k], x[k], opts[k], &results[k], side, cgws, spws);
+                for (int k : large) cg_solve_ws(mats[k], b[k], x[k], opts[k], &results[k], side, cgws, spws, false);
             }
         } catch (...) {
             cleanup();

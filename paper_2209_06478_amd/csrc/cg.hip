@@ -19,6 +19,8 @@
 // A d = r/||r|| with FP32 vectors and FP32-accumulated SpMV, while its dot
 // products are accumulated in FP64.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "core.hpp"
@@ -241,29 +243,97 @@ size_t cg_workspace_bytes(i64 n, bool ir) {
 
 static unsigned vec_grid(i64 n) { return (unsigned)std::max<i64>(1, std::min<i64>(CGG, (n + CGB - 1) / CGB)); }
 
+// One CG iteration: SpMV, p.q, x/r update, p update.  Every kernel checks
+// the state's done flag first, so iterations enqueued past convergence cost
+// only their launches.
+template <class X>
+static void enqueue_iteration(dsm_matrix m, X *x, X *r, X *p, X *q, double *part_a, double *part_b, CgState *st,
+                              int vdt, hipStream_t s, Workspace &spws) {
+    const i64 n = m->nrows;
+    spmv(m, m->P, p, q, vdt, m->variant, s, &spws, &st->done);
+    hipLaunchKernelGGL((k_cg_dot_pq<X>), dim3(CGG), dim3(CGB), 0, s, n, p, q, part_a, st);
+    hipLaunchKernelGGL((k_cg_update_xr<X>), dim3(CGG), dim3(CGB), 0, s, n, x, r, p, q, part_a, part_b, st);
+    hipLaunchKernelGGL((k_cg_update_p<X>), dim3(CGG), dim3(CGB), 0, s, n, r, p, part_b, st);
+}
+
+static bool graphs_enabled() {
+    const char *e = getenv("DSM_CG_GRAPH");
+    return !(e && e[0] == '0');
+}
+
 // Runs CG on (b, x) with vectors of type X.  Uses buffers r, p, q, part_*.
-// Returns the final state (read back).
+// The loop is replayed in chunks of `check_every` iterations from a HIP
+// graph captured once per (matrix payload, buffers, chunk) and kept in
+// `cgws`; the host reads the device state back once per chunk.  Returns the
+// final state.
 template <class X>
 static CgState run_cg(dsm_matrix m, const X *b, X *x, X *r, X *p, X *q, double *part_a, double *part_b,
                       CgState *st, int vdt, double tol, long long maxit, int check_every, hipStream_t s,
-                      Workspace &spws) {
+                      Workspace &spws, Workspace &cgws, bool use_graph) {
     const i64 n = m->nrows;
-    // grid of the vector kernels is always CGG so every partial slot is written
-    const unsigned G = CGG;
-    (void)vec_grid;
     spmv(m, m->P, x, q, vdt, m->variant, s, &spws);
-    hipLaunchKernelGGL((k_cg_init<X>), dim3(G), dim3(CGB), 0, s, n, b, q, r, p, part_a);
+    hipLaunchKernelGGL((k_cg_init<X>), dim3(CGG), dim3(CGB), 0, s, n, b, q, r, p, part_a);
     hipLaunchKernelGGL(k_cg_init_state, dim3(1), dim3(CGB), 0, s, part_a, st, tol, maxit);
     DSM_HIP(hipGetLastError());
     CgState h{};
+    hipStream_t gs = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (use_graph && graphs_enabled()) {
+        const Payload &P = m->P;
+        char key[512];
+        snprintf(key, sizeof key, "%p|%d|%d|%d|%lld|%lld|%lld|%lld|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%p|%lld",
+                 (void *)m, P.fmt, P.vdt, m->variant, (long long)P.ndiag, (long long)P.K, (long long)P.csr_nnz,
+                 (long long)P.coo_nnz, (void *)P.rp, (void *)P.dval, (void *)P.evl, (void *)P.cval, (void *)x,
+                 (void *)r, (void *)p, (void *)q, (void *)part_a, (void *)part_b, vdt, check_every, spws.p,
+                 (long long)n);
+        // private replay stream (default priority, non-blocking)
+        if (!cgws.stream) DSM_HIP(hipStreamCreateWithFlags(&cgws.stream, hipStreamNonBlocking));
+        gs = cgws.stream;
+        // the scratch the SpMV needs is sized by the eager SpMV above
+        if (cgws.graph_key != std::string(key) + "|" + std::to_string((uintptr_t)st)) {
+            if (cgws.graph) (void)hipGraphExecDestroy((hipGraphExec_t)cgws.graph);
+            cgws.graph = nullptr;
+            cgws.graph_key.clear();
+            hipGraph_t g = nullptr;
+            bool ok = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                // the capture is always closed, also when enqueueing fails
+                try {
+                    for (int j = 0; j < check_every; j++)
+                        enqueue_iteration<X>(m, x, r, p, q, part_a, part_b, st, vdt, gs, spws);
+                } catch (...) {
+                    ok = false;
+                }
+                hipError_t ec = hipStreamEndCapture(gs, &g);
+                ok = ok && ec == hipSuccess && g != nullptr;
+            }
+            hipGraphExec_t ex = nullptr;
+            if (ok) ok = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            if (ok) {
+                cgws.graph = ex;
+                cgws.graph_key = std::string(key) + "|" + std::to_string((uintptr_t)st);
+            }
+        }
+        exec = (hipGraphExec_t)cgws.graph;
+    }
+    if (exec) {
+        DSM_HIP(hipStreamSynchronize(s));  // init work done before the replays
+        long long done_iters = 0;
+        for (;;) {
+            DSM_HIP(hipGraphLaunch(exec, gs));
+            done_iters += check_every;
+            DSM_HIP(hipMemcpyAsync(&h, st, sizeof(CgState), hipMemcpyDeviceToHost, gs));
+            DSM_HIP(hipStreamSynchronize(gs));
+            if (h.done || done_iters >= maxit) break;
+        }
+        return h;
+    }
     long long enq = 0;
     for (;;) {
-        for (int j = 0; j < check_every && enq < maxit; j++, enq++) {
-            spmv(m, m->P, p, q, vdt, m->variant, s, &spws);
-            hipLaunchKernelGGL((k_cg_dot_pq<X>), dim3(G), dim3(CGB), 0, s, n, p, q, part_a, st);
-            hipLaunchKernelGGL((k_cg_update_xr<X>), dim3(G), dim3(CGB), 0, s, n, x, r, p, q, part_a, part_b, st);
-            hipLaunchKernelGGL((k_cg_update_p<X>), dim3(G), dim3(CGB), 0, s, n, r, p, part_b, st);
-        }
+        for (int j = 0; j < check_every && enq < maxit; j++, enq++)
+            enqueue_iteration<X>(m, x, r, p, q, part_a, part_b, st, vdt, s, spws);
         DSM_HIP(hipGetLastError());
         DSM_HIP(hipMemcpyAsync(&h, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
         DSM_HIP(hipStreamSynchronize(s));
@@ -289,7 +359,7 @@ static double true_relres(dsm_matrix m, const double *b, const double *x, CgBuff
 static int default_check_every(i64 n) { return n < 100000 ? 32 : 8; }
 
 void cg_solve_ws(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o, dsm_cg_result *res, hipStream_t s,
-                 Workspace &cgws, Workspace &spws) {
+                 Workspace &cgws, Workspace &spws, bool use_graph) {
     DSM_CHECK(m->nrows == m->ncols, DSM_E_UNSUPPORTED, "CG needs a square matrix");
     const i64 n = m->nrows;
     long long maxit = o.maxit > 0 ? o.maxit : std::min<long long>(10 * std::max<i64>(n, 1), 20000);
@@ -307,7 +377,7 @@ void cg_solve_ws(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o,
     }
     if (!ir) {
         CgState h = run_cg<double>(m, b, x, B.r, B.p, B.q, B.part_a, B.part_b, B.st, DSM_F64, o.tol, maxit, every, s,
-                                   spws);
+                                   spws, cgws, use_graph);
         R.iters = h.iters;
         R.relres = h.relres;
         R.status = h.done == 1 ? DSM_OK : h.done == 3 ? DSM_E_BREAKDOWN : DSM_E_NOT_CONVERGED;
@@ -346,7 +416,8 @@ void cg_solve_ws(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o,
         DSM_HIP(hipGetLastError());
         // the scaled residual r32 is the inner right-hand side, d32 the inner iterate
         CgState h = run_cg<float>(m, B.r32, B.d32, B.ri32, B.p32, B.q32, B.part_a, B.part_b, B.st2, DSM_F32,
-                                  inner_tol, std::max<long long>(1, maxit - inner_total), every, s, spws);
+                                  inner_tol, std::max<long long>(1, maxit - inner_total), every, s, spws,
+                                  cgws, use_graph);
         inner_total += h.iters;
         if (h.done == 3 && h.iters <= 1) {
             status = DSM_E_BREAKDOWN;
@@ -389,7 +460,7 @@ DSM_API dsm_status dsm_cg_solve(dsm_matrix m, const double *b, double *x, const 
         if (opts) o = *opts;
         DSM_CHECK(o.tol >= 0, DSM_E_INVALID, "negative tolerance");
         hipStream_t s = (hipStream_t)stream;
-        cg_solve_ws(m, b, x, o, &R, s, m->cgws, m->ws);
+        cg_solve_ws(m, b, x, o, &R, s, m->cgws, m->ws, true);
         m->last_stream = s;
     });
     if (result) *result = R;

@@ -70,10 +70,15 @@ struct Payload {
     }
 };
 
-// Scratch buffers the SpMV/CG paths reuse between calls.
+// Scratch buffers the SpMV/CG paths reuse between calls.  A CG workspace
+// also keeps the last captured iteration chunk (a HIP graph) with the key it
+// was captured for, and a private stream to replay it on.
 struct Workspace {
     void *p = nullptr;
     size_t bytes = 0;
+    void *graph = nullptr;  // hipGraphExec_t
+    std::string graph_key;
+    hipStream_t stream = nullptr;
 };
 
 }  // namespace dsm
@@ -123,18 +128,26 @@ void row_stats(dsm_matrix m, i64 *out, hipStream_t s);
 
 // ---------------------------------------------------------------- spmv.hip
 // y = A x for one payload; vector dtype F64 or F32.  `scratch` holds the
-// COO tile partials (the matrix's own workspace when null).
+// COO tile partials (the matrix's own workspace when null).  When `stop`
+// is given, every kernel returns at once if *stop is non-zero (the CG loop's
+// convergence flag).
 void spmv(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant,
-          hipStream_t s, Workspace *scratch = nullptr);
+          hipStream_t s, Workspace *scratch = nullptr, const int *stop = nullptr);
 // Algorithmic bytes one SpMV must move (x read once, y written once).
 double spmv_bytes(const dsm_matrix_s *m, const Payload &P, int vec_dtype);
-// Number of CSR kernel variants (index 0 = adaptive).
+// Number of CSR kernel variants (index 0 = adaptive) and of DIA/ELL sweep
+// variants (tile order x rows per thread x streaming loads).
 constexpr int CSR_VARIANTS = 8;
+constexpr int SWEEP_VARIANT_COUNT = 16;
 
 // ---------------------------------------------------------------- cg.hip / batched.hip
 // CG with caller-provided workspaces (vectors/scalars, SpMV scratch).
+// `use_graph` replays the iteration chunks from a captured HIP graph; the
+// multi-threaded callers (server workers, batched side stream) pass false,
+// since a capture in one thread makes device-wide synchronisation in
+// another thread fail.
 void cg_solve_ws(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o, dsm_cg_result *res,
-                 hipStream_t s, Workspace &cgws, Workspace &spws);
+                 hipStream_t s, Workspace &cgws, Workspace &spws, bool use_graph);
 size_t cg_workspace_bytes(i64 n, bool ir);
 // One-workgroup solver: eligibility, per-request device bytes, and timing
 // of one solve of `P` with `lanes` (CSR) for `iters` iterations (us).

@@ -181,14 +181,17 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
                 variants = f == DSM_CSR ? std::vector<int>{1, 2, 4, 8, 16, 32} : std::vector<int>{1};
             } else if (o.tune_variant) {
                 if (f == DSM_CSR) variants = {0, 7, 2, 3, 4, 5, 6};
-                else if (f == DSM_DIA || f == DSM_ELL) variants = {0, 1};
+                else if (f == DSM_DIA || f == DSM_ELL || f == DSM_HDC || f == DSM_HYB)
+                    variants = {0, 1, 2, 4, 8, 10, 12};
             }
             double tf = 0;
             int vf = 0;
             for (int v : variants) {
                 double t = o.target == 1 ? time_batched_solve(m, P, v, BATCH_TUNE_ITERS, s)
                                          : time_spmv(m, P, v, x, y, vec, o.warmup, o.reps, s);
-                if (v == variants[0] || t < tf) {
+                // a later variant must be clearly faster (1%) to displace an
+                // earlier one, so the choice does not flip on timing noise
+                if (v == variants[0] || t < 0.99 * tf) {
                     tf = t;
                     vf = v;
                 }

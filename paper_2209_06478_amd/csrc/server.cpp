@@ -127,7 +127,7 @@ static void worker_main(dsm_server s) {
                     x = r.x;
                     o = r.o;
                 }
-                cg_solve_ws(m, b, x, o, &res[0], stream, cgws, spws);
+                cg_solve_ws(m, b, x, o, &res[0], stream, cgws, spws, false);
             }
         } catch (const Error &e) {
             err = e.status;

@@ -38,7 +38,9 @@ __device__ __forceinline__ void store_y(X *y, i64 i, X v, bool acc) {
 template <class V, class X, bool ACC, bool XCD>
 __global__ void __launch_bounds__(SB) k_csr_adaptive(const i32 *__restrict__ blocks, const i32 *__restrict__ rp,
                                                      const i32 *__restrict__ col, const V *__restrict__ val,
-                                                     const X *__restrict__ x, X *__restrict__ y) {
+                                                     const X *__restrict__ x, X *__restrict__ y,
+                                                     const int *__restrict__ stop) {
+    if (stop && *stop) return;
     __shared__ X prod[2 * RB_T];
     __shared__ X red[SB / WAVE];
     const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -71,7 +73,8 @@ __global__ void __launch_bounds__(SB) k_csr_adaptive(const i32 *__restrict__ blo
 template <class V, class X, int W, bool ACC>
 __global__ void __launch_bounds__(SB) k_csr_vector(i64 nrows, const i32 *__restrict__ rp, const i32 *__restrict__ col,
                                                    const V *__restrict__ val, const X *__restrict__ x,
-                                                   X *__restrict__ y) {
+                                                   X *__restrict__ y, const int *__restrict__ stop) {
+    if (stop && *stop) return;
     const i64 row = ((i64)blockIdx.x * SB + threadIdx.x) / W;
     const int lane = threadIdx.x % W;
     X s = 0;
@@ -83,37 +86,76 @@ __global__ void __launch_bounds__(SB) k_csr_vector(i64 nrows, const i32 *__restr
     if (row < nrows && lane == 0) store_y(y, row, s, ACC);
 }
 
-// ---------------------------------------------------------------- DIA
-template <class V, class X, bool ACC, bool XCD>
-__global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, const i32 *__restrict__ offs,
-                                            const V *__restrict__ dval, i64 pitch, const X *__restrict__ x,
-                                            X *__restrict__ y) {
-    const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
-    const i64 i = (i64)b * SB + threadIdx.x;
-    if (i >= nrows) return;
-    X s = 0;
-#pragma unroll 3
-    for (i64 k = 0; k < ndiag; k++) {
-        const i64 j = i + offs[k];
-        if (j >= 0 && j < ncols) s += widen<X>(dval[k * pitch + i]) * x[j];
-    }
-    store_y(y, i, s, ACC);
+// ---------------------------------------------------------------- DIA / ELL
+// Variant bits shared by the DIA and ELL sweeps: bit 0 turns the XCD-aware
+// tile order off, bits 1-2 give log2 of the rows per thread (1, 2, 4; each
+// thread keeps that many independent accumulators, so more loads are in
+// flight), bit 3 streams the matrix values with non-temporal loads (they are
+// read once per SpMV; x and y keep the caches).
+template <class V, bool NT>
+__device__ __forceinline__ V ld_stream(const V *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <>
+__device__ __forceinline__ bf16 ld_stream<bf16, true>(const bf16 *p) {
+    bf16 r;
+    r.bits = __builtin_nontemporal_load(&p->bits);
+    return r;
 }
 
-// ---------------------------------------------------------------- ELL
-template <class V, class X, bool ACC, bool XCD>
-__global__ void __launch_bounds__(SB) k_ell(i64 nrows, i64 K, i64 pitch, const i32 *__restrict__ ecol,
-                                            const V *__restrict__ evl, const X *__restrict__ x, X *__restrict__ y) {
+template <class V, class X, bool ACC, bool XCD, int R, bool NT>
+__global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, const i32 *__restrict__ offs,
+                                            const V *__restrict__ dval, i64 pitch, const X *__restrict__ x,
+                                            X *__restrict__ y, const int *__restrict__ stop) {
+    if (stop && *stop) return;
     const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
-    const i64 i = (i64)b * SB + threadIdx.x;
-    if (i >= nrows) return;
-    X s = 0;
-#pragma unroll 3
-    for (i64 k = 0; k < K; k++) {
-        const i32 c = ecol[k * pitch + i];
-        if (c >= 0) s += widen<X>(evl[k * pitch + i]) * x[c];
+    const i64 i0 = (i64)b * SB * R + threadIdx.x;
+    X s[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) s[r] = 0;
+    for (i64 k = 0; k < ndiag; k++) {
+        const i64 off = offs[k];
+        const V *dk = dval + k * pitch;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const i64 i = i0 + (i64)r * SB;
+            const i64 j = i + off;
+            if (i < nrows && j >= 0 && j < ncols) s[r] += widen<X>(ld_stream<V, NT>(dk + i)) * x[j];
+        }
     }
-    store_y(y, i, s, ACC);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const i64 i = i0 + (i64)r * SB;
+        if (i < nrows) store_y(y, i, s[r], ACC);
+    }
+}
+
+template <class V, class X, bool ACC, bool XCD, int R, bool NT>
+__global__ void __launch_bounds__(SB) k_ell(i64 nrows, i64 K, i64 pitch, const i32 *__restrict__ ecol,
+                                            const V *__restrict__ evl, const X *__restrict__ x, X *__restrict__ y,
+                                            const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const i64 i0 = (i64)b * SB * R + threadIdx.x;
+    X s[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) s[r] = 0;
+    for (i64 k = 0; k < K; k++) {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const i64 i = i0 + (i64)r * SB;
+            if (i < nrows) {
+                const i32 c = ld_stream<i32, NT>(ecol + k * pitch + i);
+                if (c >= 0) s[r] += widen<X>(ld_stream<V, NT>(evl + k * pitch + i)) * x[c];
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const i64 i = i0 + (i64)r * SB;
+        if (i < nrows) store_y(y, i, s[r], ACC);
+    }
 }
 
 // ---------------------------------------------------------------- COO
@@ -128,7 +170,9 @@ template <class V, class X, int E, bool ACC>
 __global__ void __launch_bounds__(SB) k_coo_tiles(i64 nnz, i64 nrows, const i32 *__restrict__ row,
                                                   const i32 *__restrict__ col, const V *__restrict__ val,
                                                   const X *__restrict__ x, X *__restrict__ y,
-                                                  X *__restrict__ head_val, X *__restrict__ tail_val) {
+                                                  X *__restrict__ head_val, X *__restrict__ tail_val,
+                                                  const int *__restrict__ stop) {
+    if (stop && *stop) return;
     constexpr i32 SENT = INT32_MAX;
     constexpr i64 TE = (i64)WAVE * E;
     const int lane = threadIdx.x % WAVE;
@@ -235,7 +279,8 @@ __global__ void __launch_bounds__(SB) k_coo_tiles(i64 nnz, i64 nrows, const i32 
 // tail to the heads of the following tiles, in tile order.
 template <class X, int E, bool ACC>
 __global__ void k_coo_fixup(i64 nnz, i64 ntiles, const i32 *__restrict__ row, const X *__restrict__ head_val,
-                            const X *__restrict__ tail_val, X *__restrict__ y) {
+                            const X *__restrict__ tail_val, X *__restrict__ y, const int *__restrict__ stop) {
+    if (stop && *stop) return;
     constexpr i64 TE = (i64)WAVE * E;
     const i64 u = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= ntiles) return;
@@ -254,7 +299,8 @@ __global__ void k_coo_fixup(i64 nnz, i64 ntiles, const i32 *__restrict__ row, co
 }
 
 template <class X>
-__global__ void k_fill(i64 n, X *y, X v) {
+__global__ void k_fill(i64 n, X *y, X v, const int *stop) {
+    if (stop && *stop) return;
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[i] = v;
 }
@@ -262,10 +308,10 @@ __global__ void k_fill(i64 n, X *y, X v) {
 // ================================================================ host dispatch
 template <class V, class X>
 static void coo_launch(dsm_matrix m, i64 nnz, const i32 *row, const i32 *col, const V *val, const X *x, X *y,
-                       bool acc, hipStream_t s, Workspace *scratch) {
+                       bool acc, hipStream_t s, Workspace *scratch, const int *stop) {
     const i64 n = m->nrows;
     if (nnz == 0) {
-        if (!acc && n > 0) hipLaunchKernelGGL(k_fill<X>, dim3(grid_for(n, SB)), dim3(SB), 0, s, n, y, (X)0);
+        if (!acc && n > 0) hipLaunchKernelGGL(k_fill<X>, dim3(grid_for(n, SB)), dim3(SB), 0, s, n, y, (X)0, stop);
         return;
     }
     const i64 ntiles = (nnz + COO_TE - 1) / COO_TE;
@@ -274,19 +320,20 @@ static void coo_launch(dsm_matrix m, i64 nnz, const i32 *row, const i32 *col, co
     const unsigned g = grid_for(ntiles, SB / WAVE);
     if (acc) {
         hipLaunchKernelGGL((k_coo_tiles<V, X, COO_E, true>), dim3(g), dim3(SB), 0, s, nnz, n, row, col, val, x, y,
-                           head, tail);
+                           head, tail, stop);
         hipLaunchKernelGGL((k_coo_fixup<X, COO_E, true>), dim3(grid_for(ntiles, SB)), dim3(SB), 0, s, nnz, ntiles,
-                           row, head, tail, y);
+                           row, head, tail, y, stop);
     } else {
         hipLaunchKernelGGL((k_coo_tiles<V, X, COO_E, false>), dim3(g), dim3(SB), 0, s, nnz, n, row, col, val, x, y,
-                           head, tail);
+                           head, tail, stop);
         hipLaunchKernelGGL((k_coo_fixup<X, COO_E, false>), dim3(grid_for(ntiles, SB)), dim3(SB), 0, s, nnz, ntiles,
-                           row, head, tail, y);
+                           row, head, tail, y, stop);
     }
 }
 
 template <class V, class X, bool ACC>
-static void csr_launch(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s) {
+static void csr_launch(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s,
+                       const int *stop) {
     const i64 n = m->nrows;
     if (n == 0) return;
     const V *val = (const V *)P.val;
@@ -294,15 +341,16 @@ static void csr_launch(dsm_matrix m, const Payload &P, const X *x, X *y, int var
         if (P.nrblocks == 0) return;
         if (variant == 0)
             hipLaunchKernelGGL((k_csr_adaptive<V, X, ACC, true>), dim3((unsigned)P.nrblocks), dim3(SB), 0, s,
-                               P.rblocks, P.rp, P.col, val, x, y);
+                               P.rblocks, P.rp, P.col, val, x, y, stop);
         else
             hipLaunchKernelGGL((k_csr_adaptive<V, X, ACC, false>), dim3((unsigned)P.nrblocks), dim3(SB), 0, s,
-                               P.rblocks, P.rp, P.col, val, x, y);
+                               P.rblocks, P.rp, P.col, val, x, y, stop);
         return;
     }
     const int W = 1 << variant;  // 2 .. 64
     const unsigned g = grid_for(n * W, SB);
-#define VEC(WW) hipLaunchKernelGGL((k_csr_vector<V, X, WW, ACC>), dim3(g), dim3(SB), 0, s, n, P.rp, P.col, val, x, y)
+#define VEC(WW) \
+    hipLaunchKernelGGL((k_csr_vector<V, X, WW, ACC>), dim3(g), dim3(SB), 0, s, n, P.rp, P.col, val, x, y, stop)
     switch (W) {
     case 2: VEC(2); break;
     case 4: VEC(4); break;
@@ -314,43 +362,56 @@ static void csr_launch(dsm_matrix m, const Payload &P, const X *x, X *y, int var
 #undef VEC
 }
 
+template <class V, class X, bool XCD, int R, bool NT>
+static void sweep_launch(dsm_matrix m, const Payload &P, const X *x, X *y, hipStream_t s, const int *stop) {
+    const i64 n = m->nrows;
+    const unsigned g = grid_for(n, SB * R);
+    if (P.fmt == DSM_DIA || P.fmt == DSM_HDC)
+        hipLaunchKernelGGL((k_dia<V, X, false, XCD, R, NT>), dim3(g), dim3(SB), 0, s, n, m->ncols, P.ndiag, P.offs,
+                           (const V *)P.dval, P.pitch, x, y, stop);
+    else
+        hipLaunchKernelGGL((k_ell<V, X, false, XCD, R, NT>), dim3(g), dim3(SB), 0, s, n, P.K, P.pitch, P.ecol,
+                           (const V *)P.evl, x, y, stop);
+}
+
+template <class V, class X, bool XCD, bool NT>
+static void sweep_r(dsm_matrix m, const Payload &P, const X *x, X *y, int lr, hipStream_t s, const int *stop) {
+    if (lr == 0) sweep_launch<V, X, XCD, 1, NT>(m, P, x, y, s, stop);
+    else if (lr == 1) sweep_launch<V, X, XCD, 2, NT>(m, P, x, y, s, stop);
+    else sweep_launch<V, X, XCD, 4, NT>(m, P, x, y, s, stop);
+}
+
+template <class V, class X>
+static void sweep(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s, const int *stop) {
+    const bool xcd = !(variant & 1), nt = (variant >> 3) & 1;
+    const int lr = (variant >> 1) & 3;
+    if (xcd && nt) sweep_r<V, X, true, true>(m, P, x, y, lr, s, stop);
+    else if (xcd) sweep_r<V, X, true, false>(m, P, x, y, lr, s, stop);
+    else if (nt) sweep_r<V, X, false, true>(m, P, x, y, lr, s, stop);
+    else sweep_r<V, X, false, false>(m, P, x, y, lr, s, stop);
+}
+
 template <class V, class X>
 static void spmv_typed(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s,
-                       Workspace *scratch) {
-    const i64 n = m->nrows, nc = m->ncols;
-    const unsigned g = grid_for(n, SB);
-    const bool xcd = variant != 1;
+                       Workspace *scratch, const int *stop) {
+    const i64 n = m->nrows;
     switch (P.fmt) {
     case DSM_CSR:
-        csr_launch<V, X, false>(m, P, x, y, variant, s);
+        csr_launch<V, X, false>(m, P, x, y, variant, s, stop);
         break;
     case DSM_COO:
-        coo_launch<V, X>(m, P.coo_nnz, P.crow, P.ccol, (const V *)P.cval, x, y, false, s, scratch);
+        coo_launch<V, X>(m, P.coo_nnz, P.crow, P.ccol, (const V *)P.cval, x, y, false, s, scratch, stop);
         break;
     case DSM_DIA:
     case DSM_HDC:
-        if (n > 0) {
-            if (xcd)
-                hipLaunchKernelGGL((k_dia<V, X, false, true>), dim3(g), dim3(SB), 0, s, n, nc, P.ndiag, P.offs,
-                                   (const V *)P.dval, P.pitch, x, y);
-            else
-                hipLaunchKernelGGL((k_dia<V, X, false, false>), dim3(g), dim3(SB), 0, s, n, nc, P.ndiag, P.offs,
-                                   (const V *)P.dval, P.pitch, x, y);
-        }
-        if (P.fmt == DSM_HDC && P.csr_nnz > 0) csr_launch<V, X, true>(m, P, x, y, 0, s);
+        if (n > 0) sweep<V, X>(m, P, x, y, variant, s, stop);
+        if (P.fmt == DSM_HDC && P.csr_nnz > 0) csr_launch<V, X, true>(m, P, x, y, 0, s, stop);
         break;
     case DSM_ELL:
     case DSM_HYB:
-        if (n > 0) {
-            if (xcd)
-                hipLaunchKernelGGL((k_ell<V, X, false, true>), dim3(g), dim3(SB), 0, s, n, P.K, P.pitch, P.ecol,
-                                   (const V *)P.evl, x, y);
-            else
-                hipLaunchKernelGGL((k_ell<V, X, false, false>), dim3(g), dim3(SB), 0, s, n, P.K, P.pitch, P.ecol,
-                                   (const V *)P.evl, x, y);
-        }
+        if (n > 0) sweep<V, X>(m, P, x, y, variant, s, stop);
         if (P.fmt == DSM_HYB && P.coo_nnz > 0)
-            coo_launch<V, X>(m, P.coo_nnz, P.crow, P.ccol, (const V *)P.cval, x, y, true, s, scratch);
+            coo_launch<V, X>(m, P.coo_nnz, P.crow, P.ccol, (const V *)P.cval, x, y, true, s, scratch, stop);
         break;
     default:
         fail(DSM_E_INVALID, "spmv: unknown format");
@@ -359,23 +420,23 @@ static void spmv_typed(dsm_matrix m, const Payload &P, const X *x, X *y, int var
 }
 
 void spmv(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant, hipStream_t s,
-          Workspace *scratch) {
+          Workspace *scratch, const int *stop) {
     DSM_CHECK(vdt == DSM_F64 || vdt == DSM_F32, DSM_E_UNSUPPORTED, "spmv: vectors must be F64 or F32");
     if (vdt == DSM_F64) {
         const double *xx = (const double *)x;
         double *yy = (double *)y;
         switch (P.vdt) {
-        case DSM_F64: spmv_typed<double, double>(m, P, xx, yy, variant, s, scratch); break;
-        case DSM_F32: spmv_typed<float, double>(m, P, xx, yy, variant, s, scratch); break;
-        default: spmv_typed<bf16, double>(m, P, xx, yy, variant, s, scratch); break;
+        case DSM_F64: spmv_typed<double, double>(m, P, xx, yy, variant, s, scratch, stop); break;
+        case DSM_F32: spmv_typed<float, double>(m, P, xx, yy, variant, s, scratch, stop); break;
+        default: spmv_typed<bf16, double>(m, P, xx, yy, variant, s, scratch, stop); break;
         }
     } else {
         const float *xx = (const float *)x;
         float *yy = (float *)y;
         switch (P.vdt) {
-        case DSM_F64: spmv_typed<double, float>(m, P, xx, yy, variant, s, scratch); break;
-        case DSM_F32: spmv_typed<float, float>(m, P, xx, yy, variant, s, scratch); break;
-        default: spmv_typed<bf16, float>(m, P, xx, yy, variant, s, scratch); break;
+        case DSM_F64: spmv_typed<double, float>(m, P, xx, yy, variant, s, scratch, stop); break;
+        case DSM_F32: spmv_typed<float, float>(m, P, xx, yy, variant, s, scratch, stop); break;
+        default: spmv_typed<bf16, float>(m, P, xx, yy, variant, s, scratch, stop); break;
         }
     }
 }

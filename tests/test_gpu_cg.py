@@ -99,3 +99,29 @@ def test_cg_rejects_rectangular():
     with pytest.raises(dsm.DsmError):
         A.cg(torch.ones(p.nrows, dtype=torch.float64, device=dev))
     A.close()
+
+
+def test_cg_graph_replay_matches_eager():
+    """The loop replayed from a captured HIP graph gives the same bits as
+    eager launches, on every replay, with eager work in between."""
+    import os
+    torch, dev = torch_dev()
+    p = problem("hpcg16")
+    A = make_matrix(p)
+    A.convert("dia")
+    b = torch.from_numpy(p.b).to(dev)
+    os.environ["DSM_CG_GRAPH"] = "0"
+    xe, re = A.cg(b)
+    xe = xe.cpu().numpy()
+    try:
+        for rep in range(3):
+            os.environ["DSM_CG_GRAPH"] = "1"
+            xg, rg = A.cg(b)
+            assert rg["iters"] == re["iters"], rep
+            assert np.array_equal(xg.cpu().numpy().view(np.uint64), xe.view(np.uint64)), rep
+            os.environ["DSM_CG_GRAPH"] = "0"
+            xe2, _ = A.cg(b)
+            assert np.array_equal(xe2.cpu().numpy().view(np.uint64), xe.view(np.uint64)), rep
+    finally:
+        os.environ.pop("DSM_CG_GRAPH", None)
+    A.close()

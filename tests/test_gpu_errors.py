@@ -14,7 +14,7 @@ def test_invalid_csr_rejected():
     ctx = dsm.Context(0)
     bad = [
         ([1, 2, 3], [0, 1, 1]),      # row_ptr[0] != 0
-        ([0, 2, 2], [0, 1]),         # row_ptr[n] != nnz
+        ([0, 2, 3], [0, 1]),         # row_ptr[n] != nnz
         ([0, 2, 3], [1, 0, 1]),      # unsorted row
         ([0, 2, 3], [1, 1, 1]),      # duplicate
         ([0, 2, 3], [0, 5, 1]),      # column out of range

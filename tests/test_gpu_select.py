@@ -47,9 +47,9 @@ def test_select_is_near_best(name):
             continue
         B = make_matrix(p)
         B.convert(f)
-        if f in ("dia", "ell", "csr"):
+        if f in ("dia", "ell", "csr", "hdc", "hyb"):
             ts = []
-            for v in ([0, 7, 2, 3, 4, 5, 6] if f == "csr" else [0, 1]):
+            for v in ([0, 7, 2, 3, 4, 5, 6] if f == "csr" else [0, 1, 2, 4, 8, 10, 12]):
                 B.variant = v
                 ts.append(median_us(B, x, y))
             t = min(ts)

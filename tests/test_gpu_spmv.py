@@ -32,7 +32,7 @@ def run_formats(name, formats=FORMATS, tol=1e-14):
                 out[f] = "infeasible"
                 continue
             raise
-        variants = range(8) if f == "csr" else ([0, 1] if f in ("dia", "ell") else [0])
+        variants = range(8) if f == "csr" else (range(16) if f in ("dia", "ell", "hdc", "hyb") else [0])
         for v in variants:
             A.variant = v
             y = A.spmv(xt)
