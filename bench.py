@@ -207,6 +207,30 @@ def serving_bench(dsm, ctx, torch, dev, nreq=10000, load=0.8, seed=0x5E4E):
             "sequential_fp64_csr": seq}
 
 
+def irregular_bench(dsm, ctx, torch, dev):
+    """Format selection on the irregular 1M-row matrices (Zipf row lengths,
+    banded with 30% fill), FP64 and FP32 values: per-format SpMV time and
+    GB/s, the chosen format and its speed-up over fixed CSR."""
+    import inputs
+    out = {}
+    for name, gen in (("zipf_1m", inputs.zipf), ("banded_1m", inputs.banded)):
+        log(f"[bench] selection on {name}")
+        p = gen()
+        for vdt in ("f64", "f32"):
+            A = dsm.Matrix.from_csr(ctx, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
+            rep = A.select(use_cache=False, value_dtype=vdt)
+            t = {f: us for f, us in rep["median_us"].items() if rep["status"][f] == 0}
+            gbps = {f: round(rep["bytes"][f] / (t[f] * 1e-6) / 1e9, 1) for f in t}
+            csr_equiv = {f: round(rep["bytes"]["csr"] / (t[f] * 1e-6) / 1e9, 1) for f in t} if "csr" in t else None
+            out[f"{name}_{vdt}"] = {"nnz": p.nnz, "chosen": rep["chosen"], "variant": rep["chosen_variant"],
+                                    "median_us": {f: round(v, 2) for f, v in t.items()}, "gbps": gbps,
+                                    "csr_equivalent_gbps": csr_equiv,
+                                    "status": rep["status"],
+                                    "speedup_vs_csr": round(t["csr"] / t[rep["chosen"]], 3) if "csr" in t else None}
+            A.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,6 +242,7 @@ def main():
     ap.add_argument("--only-spmv", action="store_true", help="skip selection/CG (profiling runs)")
     ap.add_argument("--no-ir", action="store_true", help="skip the mixed-precision CG leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-irregular", action="store_true", help="skip the irregular-matrix selection leg")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--format", default=None, help="force a format instead of selecting")
     ap.add_argument("--variant", type=int, default=None, help="kernel variant with --format")
@@ -333,6 +358,7 @@ def main():
               "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
               "ms_per_iter": round(float(lat.mean()) / max(res["iters"], 1), 4)}
 
+    irr = None if (args.only_spmv or args.no_irregular) else irregular_bench(dsm, ctx, torch, dev)
     ir = None if (args.only_spmv or args.no_ir) else ir_bench(dsm, ctx, torch, dev)
     serve = None if (args.only_spmv or args.no_serve) else serving_bench(dsm, ctx, torch, dev,
                                                                           nreq=args.serve_requests)
@@ -362,6 +388,7 @@ def main():
         "select": sel,
         "copy_probe": copy,
         "cg": cg,
+        "irregular": irr,
         "ir_cg": ir,
         "serving": serve,
         "cpu_baseline": cpu,

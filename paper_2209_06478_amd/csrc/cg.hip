@@ -42,11 +42,22 @@ struct CgState {
     int pad;
 };
 
-// Every workgroup reduces the same CGG partials in the same order.
-__device__ __forceinline__ double reduce_partials(const double *part, double *lds) {
+// Every workgroup reduces the same `count` partials in the same order.
+__device__ __forceinline__ double reduce_partials(const double *part, double *lds, int count = CGG) {
     double v = 0;
-    for (int i = threadIdx.x; i < CGG; i += blockDim.x) v += part[i];
+    for (int i = threadIdx.x; i < count; i += blockDim.x) v += part[i];
     return block_sum(v, lds);
+}
+
+// Reads the solve's done flag once per workgroup and shares it through LDS,
+// so every wave of the workgroup takes the same early exit even while
+// workgroup 0 of the same launch is writing the flag (the barriers later in
+// the kernel must see all waves).
+__device__ __forceinline__ bool wg_done(const int *flag) {
+    __shared__ int s_done;
+    if (threadIdx.x == 0) s_done = *(volatile const int *)flag;
+    __syncthreads();
+    return s_done != 0;
 }
 
 template <class X>
@@ -82,7 +93,7 @@ __global__ void __launch_bounds__(CGB) k_cg_init_state(const double *part, CgSta
 template <class X>
 __global__ void __launch_bounds__(CGB) k_cg_dot_pq(i64 n, const X *p, const X *q, double *part, CgState *st) {
     __shared__ double lds[CGB / WAVE];
-    if (st->done) return;
+    if (wg_done(&st->done)) return;
     double acc = 0;
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
         acc += (double)p[i] * (double)q[i];
@@ -97,7 +108,7 @@ template <class X>
 __global__ void __launch_bounds__(CGB) k_cg_update_xr(i64 n, X *x, X *r, const X *p, const X *q,
                                                        const double *part_pq, double *part_rr, CgState *st) {
     __shared__ double lds[CGB / WAVE];
-    if (st->done) return;
+    if (wg_done(&st->done)) return;
     const double pq = reduce_partials(part_pq, lds);
     const long long k = st->iters;
     const double rho = st->rho[(k - 1) & 1];
@@ -127,7 +138,7 @@ __global__ void __launch_bounds__(CGB) k_cg_update_xr(i64 n, X *x, X *r, const X
 template <class X>
 __global__ void __launch_bounds__(CGB) k_cg_update_p(i64 n, const X *r, X *p, const double *part_rr, CgState *st) {
     __shared__ double lds[CGB / WAVE];
-    if (st->done) return;
+    if (wg_done(&st->done)) return;
     const double rho1 = reduce_partials(part_rr, lds);
     const long long k = st->iters;
     const double rho = st->rho[(k - 1) & 1];
@@ -194,32 +205,235 @@ __global__ void __launch_bounds__(CGB) k_apply_update(i64 n, double *x, const fl
         x[i] = x[i] + s * (double)d32[i];
 }
 
+
+// ---------------------------------------------------------------- fused iteration (DIA / ELL)
+// Two kernels per iteration instead of four.  Iteration k (parity ph = k & 1):
+//   F1: rho_{k-1} = sum of the r.r partials of the previous update; stop if
+//       converged / out of iterations; beta = rho_{k-1} / rho_{k-2} (0 at
+//       k = 1); every workgroup then forms p_k = r + beta p_{k-1} on the fly
+//       for each x entry it gathers and for its own rows (stored to the other
+//       p buffer), computes q = A p_k and partials of p_k . q.
+//   F2: alpha = rho_{k-1} / (p_k . q); x += alpha p_k; r -= alpha q; partials
+//       of r.r.
+// p_k is formed with one fused multiply-add, so the value gathered by any
+// workgroup equals the stored one bit for bit.  rho_{k-1} goes to slot
+// (k-1) & 1 (written by workgroup 0 of F1, read by F2), rho_{k-2} is read
+// from slot k & 1; the completed-iteration count is written only by F2.
+template <class X>
+__device__ __forceinline__ X p_next(X r, X pold, X beta, bool first) {
+    return first ? r : fma(beta, pold, r);
+}
+
+template <class V, class X, int R, bool XCD, bool NT, bool ELL>
+__global__ void __launch_bounds__(256) k_cgf_spmv(i64 n, i64 nd, const i32 *__restrict__ offs,
+                                                  const i32 *__restrict__ ecol, const V *__restrict__ vals, i64 pitch,
+                                                  const X *__restrict__ r, const X *__restrict__ pold,
+                                                  X *__restrict__ pnew, X *__restrict__ q,
+                                                  const double *__restrict__ part_rr, double *__restrict__ part_pq,
+                                                  CgState *st, int ph) {
+    __shared__ double lds[256 / WAVE];
+    if (wg_done(&st->done)) return;
+    const double rho1 = reduce_partials(part_rr, lds);
+    const long long done_iters = st->iters;
+    const bool first = done_iters == 0;
+    if (!first) {
+        int done = 0;
+        const double nr = sqrt(rho1);
+        if (!isfinite(rho1)) done = 3;
+        else if (nr <= st->tol * st->nr0) done = 1;
+        else if (done_iters >= st->maxit) done = 2;
+        if (done) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                st->relres = st->nr0 > 0 ? nr / st->nr0 : 0.0;
+                st->done = done;
+            }
+            return;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->rho[ph ^ 1] = rho1;
+    const X beta = first ? (X)0 : (X)(rho1 / st->rho[ph]);
+    const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const i64 i0 = (i64)b * 256 * R + threadIdx.x;
+    X s[R];
+#pragma unroll
+    for (int t = 0; t < R; t++) s[t] = 0;
+    for (i64 k = 0; k < nd; k++) {
+        if constexpr (!ELL) {
+            const i64 off = offs[k];
+            const V *dk = vals + k * pitch;
+#pragma unroll
+            for (int t = 0; t < R; t++) {
+                const i64 i = i0 + (i64)t * 256;
+                const i64 j = i + off;
+                if (i < n && j >= 0 && j < n) {
+                    const V v = ld_stream<V, NT>(dk + i);
+                    s[t] += widen<X>(v) * p_next<X>(r[j], pold[j], beta, first);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < R; t++) {
+                const i64 i = i0 + (i64)t * 256;
+                if (i < n) {
+                    const i32 c = ecol[k * pitch + i];
+                    if (c >= 0) s[t] += widen<X>(vals[k * pitch + i]) * p_next<X>(r[c], pold[c], beta, first);
+                }
+            }
+        }
+    }
+    double acc = 0;
+#pragma unroll
+    for (int t = 0; t < R; t++) {
+        const i64 i = i0 + (i64)t * 256;
+        if (i < n) {
+            const X pi = p_next<X>(r[i], pold[i], beta, first);
+            pnew[i] = pi;
+            q[i] = s[t];
+            acc += (double)pi * (double)s[t];
+        }
+    }
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) part_pq[blockIdx.x] = acc;
+}
+
+template <class X>
+__global__ void __launch_bounds__(CGB) k_cgf_update(i64 n, X *x, X *r, const X *p, const X *q,
+                                                     const double *part_pq, int npq, double *part_rr, CgState *st,
+                                                     int ph) {
+    __shared__ double lds[CGB / WAVE];
+    if (wg_done(&st->done)) return;
+    const double pq = reduce_partials(part_pq, lds, npq);
+    const double rho = st->rho[ph ^ 1];
+    if (!(pq > 0) || !isfinite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->pq = pq;
+            st->iters += 1;
+            st->done = 3;
+        }
+        return;
+    }
+    const X a = (X)(rho / pq);
+    double acc = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        x[i] = x[i] + a * p[i];
+        const X ri = r[i] - a * q[i];
+        r[i] = ri;
+        acc += (double)ri * (double)ri;
+    }
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) {
+        part_rr[blockIdx.x] = acc;
+        if (blockIdx.x == 0) {
+            st->pq = pq;
+            st->iters += 1;
+        }
+    }
+}
+
+// Whether the fused two-kernel iteration applies (square DIA/ELL payload).
+static bool fused_ok(const dsm_matrix_s *m) {
+    const char *e = getenv("DSM_CG_FUSED");
+    if (e && e[0] == '0') return false;
+    return m->nrows == m->ncols && (m->P.fmt == DSM_DIA || m->P.fmt == DSM_ELL);
+}
+
+// Partials F1 writes (one per workgroup).
+static int fused_groups(const dsm_matrix_s *m) {
+    const int lr = (m->variant >> 1) & 3;
+    const int R = lr == 0 ? 1 : (lr == 1 ? 2 : 4);
+    return (int)grid_for(m->nrows, 256 * R);
+}
+
+template <class V, class X, int R, bool XCD, bool NT>
+static void cgf_launch(dsm_matrix m, const X *r, const X *pold, X *pnew, X *q, double *part_rr, double *part_pq,
+                       CgState *st, int ph, hipStream_t s) {
+    const Payload &P = m->P;
+    const i64 n = m->nrows;
+    const unsigned g = grid_for(n, 256 * R);
+    if (P.fmt == DSM_DIA)
+        hipLaunchKernelGGL((k_cgf_spmv<V, X, R, XCD, NT, false>), dim3(g), dim3(256), 0, s, n, P.ndiag, P.offs,
+                           (const i32 *)nullptr, (const V *)P.dval, P.pitch, r, pold, pnew, q, part_rr, part_pq, st,
+                           ph);
+    else
+        hipLaunchKernelGGL((k_cgf_spmv<V, X, R, XCD, NT, true>), dim3(g), dim3(256), 0, s, n, P.K,
+                           (const i32 *)nullptr, P.ecol, (const V *)P.evl, P.pitch, r, pold, pnew, q, part_rr,
+                           part_pq, st, ph);
+}
+
+template <class V, class X, bool XCD, bool NT>
+static void cgf_r(dsm_matrix m, int lr, const X *r, const X *pold, X *pnew, X *q, double *prr, double *ppq,
+                  CgState *st, int ph, hipStream_t s) {
+    if (lr == 0) cgf_launch<V, X, 1, XCD, NT>(m, r, pold, pnew, q, prr, ppq, st, ph, s);
+    else if (lr == 1) cgf_launch<V, X, 2, XCD, NT>(m, r, pold, pnew, q, prr, ppq, st, ph, s);
+    else cgf_launch<V, X, 4, XCD, NT>(m, r, pold, pnew, q, prr, ppq, st, ph, s);
+}
+
+template <class V, class X>
+static void cgf_dispatch(dsm_matrix m, const X *r, const X *pold, X *pnew, X *q, double *prr, double *ppq,
+                         CgState *st, int ph, hipStream_t s) {
+    const int v = m->variant;
+    const bool xcd = !(v & 1), nt = (v >> 3) & 1 && m->P.fmt == DSM_DIA;
+    const int lr = (v >> 1) & 3;
+    if (xcd && nt) cgf_r<V, X, true, true>(m, lr, r, pold, pnew, q, prr, ppq, st, ph, s);
+    else if (xcd) cgf_r<V, X, true, false>(m, lr, r, pold, pnew, q, prr, ppq, st, ph, s);
+    else if (nt) cgf_r<V, X, false, true>(m, lr, r, pold, pnew, q, prr, ppq, st, ph, s);
+    else cgf_r<V, X, false, false>(m, lr, r, pold, pnew, q, prr, ppq, st, ph, s);
+}
+
+// One fused iteration with parity ph; p buffers alternate: p[ph] is written.
+template <class X>
+static void enqueue_fused(dsm_matrix m, X *x, X *r, X *pbuf[2], X *q, double *part_pq, double *part_rr,
+                          CgState *st, int ph, hipStream_t s) {
+    const i64 n = m->nrows;
+    X *pnew = pbuf[ph], *pold = pbuf[ph ^ 1];
+    switch (m->P.vdt) {
+    case DSM_F64: cgf_dispatch<double, X>(m, r, pold, pnew, q, part_rr, part_pq, st, ph, s); break;
+    case DSM_F32: cgf_dispatch<float, X>(m, r, pold, pnew, q, part_rr, part_pq, st, ph, s); break;
+    default: cgf_dispatch<bf16, X>(m, r, pold, pnew, q, part_rr, part_pq, st, ph, s); break;
+    }
+    hipLaunchKernelGGL((k_cgf_update<X>), dim3(CGG), dim3(CGB), 0, s, n, x, r, pnew, q, part_pq, fused_groups(m),
+                       part_rr, st, ph);
+}
+
 // ================================================================ host side
 struct CgBuffers {
-    // FP64 part
-    double *r = nullptr, *p = nullptr, *q = nullptr;
+    // FP64 part (p2: second p buffer of the fused iteration)
+    double *r = nullptr, *p = nullptr, *q = nullptr, *p2 = nullptr;
     double *part_a = nullptr, *part_b = nullptr, *norms = nullptr;
     CgState *st = nullptr, *st2 = nullptr;
     // FP32 inner part (IR)
-    float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr, *ri32 = nullptr;
+    float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr, *ri32 = nullptr, *p32b = nullptr;
 };
+
+// Partials per workgroup: the vector kernels use CGG, the fused SpMV one per
+// 256-row tile.
+static size_t partial_slots(i64 n) { return (size_t)std::max<i64>(CGG, n / 256 + 2); }
+
+static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Workspace bytes a solve of this matrix needs (also used for admission).
+size_t cg_workspace_bytes(i64 n, bool ir) {
+    const size_t nn = (size_t)std::max<i64>(n, 1);
+    size_t bytes = 4 * round256(nn * 8) + 2 * round256(partial_slots(n) * 8) + 8 * 256;
+    if (ir) bytes += 6 * round256(nn * 4);
+    return bytes;
+}
 
 static CgBuffers cg_buffers(dsm_matrix m, bool ir, Workspace &cgws) {
     const size_t n = (size_t)std::max<i64>(m->nrows, 1);
-    size_t bytes = 3 * ((n * 8 + 255) & ~(size_t)255) + 8 * 256 + 2 * CGG * 8;
-    if (ir) bytes += 5 * ((n * 4 + 255) & ~(size_t)255);
-    char *base = (char *)ws_get(m->ctx, cgws, bytes);
+    char *base = (char *)ws_get(m->ctx, cgws, cg_workspace_bytes(m->nrows, ir));
     CgBuffers B;
     auto take = [&](size_t sz) {
         char *p = base;
-        base += (sz + 255) & ~(size_t)255;
+        base += round256(sz);
         return (void *)p;
     };
     B.r = (double *)take(n * 8);
     B.p = (double *)take(n * 8);
     B.q = (double *)take(n * 8);
-    B.part_a = (double *)take(CGG * 8);
-    B.part_b = (double *)take(CGG * 8);
+    B.p2 = (double *)take(n * 8);
+    B.part_a = (double *)take(partial_slots(m->nrows) * 8);
+    B.part_b = (double *)take(partial_slots(m->nrows) * 8);
     B.norms = (double *)take(64);
     B.st = (CgState *)take(sizeof(CgState));
     B.st2 = (CgState *)take(sizeof(CgState));
@@ -229,16 +443,9 @@ static CgBuffers cg_buffers(dsm_matrix m, bool ir, Workspace &cgws) {
         B.q32 = (float *)take(n * 4);
         B.d32 = (float *)take(n * 4);
         B.ri32 = (float *)take(n * 4);
+        B.p32b = (float *)take(n * 4);
     }
     return B;
-}
-
-// Workspace bytes a solve of this matrix needs (for admission control).
-size_t cg_workspace_bytes(i64 n, bool ir) {
-    const size_t nn = (size_t)std::max<i64>(n, 1);
-    size_t bytes = 3 * ((nn * 8 + 255) & ~(size_t)255) + 8 * 256 + 2 * CGG * 8;
-    if (ir) bytes += 5 * ((nn * 4 + 255) & ~(size_t)255);
-    return bytes;
 }
 
 static unsigned vec_grid(i64 n) { return (unsigned)std::max<i64>(1, std::min<i64>(CGG, (n + CGB - 1) / CGB)); }
@@ -267,25 +474,37 @@ static bool graphs_enabled() {
 // `cgws`; the host reads the device state back once per chunk.  Returns the
 // final state.
 template <class X>
-static CgState run_cg(dsm_matrix m, const X *b, X *x, X *r, X *p, X *q, double *part_a, double *part_b,
+static CgState run_cg(dsm_matrix m, const X *b, X *x, X *r, X *p, X *q, X *p2, double *part_a, double *part_b,
                       CgState *st, int vdt, double tol, long long maxit, int check_every, hipStream_t s,
                       Workspace &spws, Workspace &cgws, bool use_graph) {
     const i64 n = m->nrows;
+    const bool fused = fused_ok(m);
+    if (fused) check_every += check_every & 1;  // even chunks keep the p-buffer parity
+    X *pbuf[2] = {p, p2};
+    // fused: init leaves the r.r partials where the first F1 reads them
+    double *init_part = fused ? part_b : part_a;
     spmv(m, m->P, x, q, vdt, m->variant, s, &spws);
-    hipLaunchKernelGGL((k_cg_init<X>), dim3(CGG), dim3(CGB), 0, s, n, b, q, r, p, part_a);
-    hipLaunchKernelGGL(k_cg_init_state, dim3(1), dim3(CGB), 0, s, part_a, st, tol, maxit);
+    hipLaunchKernelGGL((k_cg_init<X>), dim3(CGG), dim3(CGB), 0, s, n, b, q, r, p, init_part);
+    hipLaunchKernelGGL(k_cg_init_state, dim3(1), dim3(CGB), 0, s, init_part, st, tol, maxit);
     DSM_HIP(hipGetLastError());
+    // iteration j of a chunk (0-based) has parity (j + 1) & 1
+    auto enqueue = [&](int j, hipStream_t ss) {
+        if (fused) enqueue_fused<X>(m, x, r, pbuf, q, part_a, part_b, st, (j + 1) & 1, ss);
+        else enqueue_iteration<X>(m, x, r, p, q, part_a, part_b, st, vdt, ss, spws);
+    };
+    // the fused loop detects convergence at the start of the next iteration
+    const long long cap = maxit + (fused ? 1 : 0);
     CgState h{};
     hipStream_t gs = nullptr;
     hipGraphExec_t exec = nullptr;
     if (use_graph && graphs_enabled()) {
         const Payload &P = m->P;
         char key[512];
-        snprintf(key, sizeof key, "%p|%d|%d|%d|%lld|%lld|%lld|%lld|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%p|%lld",
+        snprintf(key, sizeof key, "%p|%d|%d|%d|%lld|%lld|%lld|%lld|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%p|%lld|%d",
                  (void *)m, P.fmt, P.vdt, m->variant, (long long)P.ndiag, (long long)P.K, (long long)P.csr_nnz,
                  (long long)P.coo_nnz, (void *)P.rp, (void *)P.dval, (void *)P.evl, (void *)P.cval, (void *)x,
-                 (void *)r, (void *)p, (void *)q, (void *)part_a, (void *)part_b, vdt, check_every, spws.p,
-                 (long long)n);
+                 (void *)r, (void *)p, (void *)q, (void *)p2, (void *)part_a, (void *)part_b, vdt, check_every,
+                 spws.p, (long long)n, (int)fused);
         // private replay stream (default priority, non-blocking)
         if (!cgws.stream) DSM_HIP(hipStreamCreateWithFlags(&cgws.stream, hipStreamNonBlocking));
         gs = cgws.stream;
@@ -299,8 +518,7 @@ static CgState run_cg(dsm_matrix m, const X *b, X *x, X *r, X *p, X *q, double *
             if (ok) {
                 // the capture is always closed, also when enqueueing fails
                 try {
-                    for (int j = 0; j < check_every; j++)
-                        enqueue_iteration<X>(m, x, r, p, q, part_a, part_b, st, vdt, gs, spws);
+                    for (int j = 0; j < check_every; j++) enqueue(j, gs);
                 } catch (...) {
                     ok = false;
                 }
@@ -326,18 +544,17 @@ static CgState run_cg(dsm_matrix m, const X *b, X *x, X *r, X *p, X *q, double *
             done_iters += check_every;
             DSM_HIP(hipMemcpyAsync(&h, st, sizeof(CgState), hipMemcpyDeviceToHost, gs));
             DSM_HIP(hipStreamSynchronize(gs));
-            if (h.done || done_iters >= maxit) break;
+            if (h.done || done_iters >= cap) break;
         }
         return h;
     }
     long long enq = 0;
     for (;;) {
-        for (int j = 0; j < check_every && enq < maxit; j++, enq++)
-            enqueue_iteration<X>(m, x, r, p, q, part_a, part_b, st, vdt, s, spws);
+        for (int j = 0; j < check_every && enq < cap; j++, enq++) enqueue(j, s);
         DSM_HIP(hipGetLastError());
         DSM_HIP(hipMemcpyAsync(&h, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
         DSM_HIP(hipStreamSynchronize(s));
-        if (h.done || enq >= maxit) break;
+        if (h.done || enq >= cap) break;
     }
     return h;
 }
@@ -376,7 +593,8 @@ void cg_solve_ws(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o,
         return;
     }
     if (!ir) {
-        CgState h = run_cg<double>(m, b, x, B.r, B.p, B.q, B.part_a, B.part_b, B.st, DSM_F64, o.tol, maxit, every, s,
+        CgState h = run_cg<double>(m, b, x, B.r, B.p, B.q, B.p2, B.part_a, B.part_b, B.st, DSM_F64, o.tol, maxit,
+                                   every, s,
                                    spws, cgws, use_graph);
         R.iters = h.iters;
         R.relres = h.relres;
@@ -415,7 +633,7 @@ void cg_solve_ws(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o,
         hipLaunchKernelGGL(k_scale_down, dim3(CGG), dim3(CGB), 0, s, n, B.r, B.norms, B.r32, B.d32);
         DSM_HIP(hipGetLastError());
         // the scaled residual r32 is the inner right-hand side, d32 the inner iterate
-        CgState h = run_cg<float>(m, B.r32, B.d32, B.ri32, B.p32, B.q32, B.part_a, B.part_b, B.st2, DSM_F32,
+        CgState h = run_cg<float>(m, B.r32, B.d32, B.ri32, B.p32, B.q32, B.p32b, B.part_a, B.part_b, B.st2, DSM_F32,
                                   inner_tol, std::max<long long>(1, maxit - inner_total), every, s, spws,
                                   cgws, use_graph);
         inner_total += h.iters;

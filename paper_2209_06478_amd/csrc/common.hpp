@@ -105,6 +105,20 @@ __device__ __forceinline__ double widen<double, bf16>(bf16 v) {
     return (double)bf16_to_float(v);
 }
 
+// Load of a matrix value or index that is read once per sweep; NT asks for
+// a non-temporal (streaming) access so it does not evict reused vectors.
+template <class V, bool NT>
+__device__ __forceinline__ V ld_stream(const V *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <>
+__device__ __forceinline__ bf16 ld_stream<bf16, true>(const bf16 *p) {
+    bf16 r;
+    r.bits = __builtin_nontemporal_load(&p->bits);
+    return r;
+}
+
 inline size_t dtype_size(int dt) { return dt == DSM_F64 ? 8 : dt == DSM_F32 ? 4 : 2; }
 inline const char *format_name(int f) {
     static const char *n[] = {"COO", "CSR", "DIA", "ELL", "HYB", "HDC"};

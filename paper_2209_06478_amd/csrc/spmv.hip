@@ -40,7 +40,10 @@ __global__ void __launch_bounds__(SB) k_csr_adaptive(const i32 *__restrict__ blo
                                                      const i32 *__restrict__ col, const V *__restrict__ val,
                                                      const X *__restrict__ x, X *__restrict__ y,
                                                      const int *__restrict__ stop) {
-    if (stop && *stop) return;
+    __shared__ int s_stop;
+    if (threadIdx.x == 0) s_stop = stop ? *stop : 0;
+    __syncthreads();
+    if (s_stop) return;
     __shared__ X prod[2 * RB_T];
     __shared__ X red[SB / WAVE];
     const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -92,18 +95,6 @@ __global__ void __launch_bounds__(SB) k_csr_vector(i64 nrows, const i32 *__restr
 // thread keeps that many independent accumulators, so more loads are in
 // flight), bit 3 streams the matrix values with non-temporal loads (they are
 // read once per SpMV; x and y keep the caches).
-template <class V, bool NT>
-__device__ __forceinline__ V ld_stream(const V *p) {
-    if constexpr (NT) return __builtin_nontemporal_load(p);
-    else return *p;
-}
-template <>
-__device__ __forceinline__ bf16 ld_stream<bf16, true>(const bf16 *p) {
-    bf16 r;
-    r.bits = __builtin_nontemporal_load(&p->bits);
-    return r;
-}
-
 template <class V, class X, bool ACC, bool XCD, int R, bool NT>
 __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, const i32 *__restrict__ offs,
                                             const V *__restrict__ dval, i64 pitch, const X *__restrict__ x,

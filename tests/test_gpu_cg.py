@@ -125,3 +125,46 @@ def test_cg_graph_replay_matches_eager():
     finally:
         os.environ.pop("DSM_CG_GRAPH", None)
     A.close()
+
+
+@pytest.mark.parametrize("fmt", ["dia", "ell"])
+@pytest.mark.parametrize("variant", [0, 4, 9])
+def test_cg_fused_iteration_matches_oracle(fmt, variant):
+    """DIA/ELL solves use the two-kernel fused iteration; it passes the same
+    oracle checks as the four-kernel loop, and the two agree within +-1 iteration."""
+    import os
+    torch, dev = torch_dev()
+    p = problem("hpcg16")
+    xo, it, _, _ = oracle.cg(p.row_ptr, p.col, p.val, p.b, tol=1e-10)
+    A = make_matrix(p)
+    A.convert(fmt)
+    A.variant = variant
+    b = torch.from_numpy(p.b).to(dev)
+    xf, rf = A.cg(b)
+    os.environ["DSM_CG_FUSED"] = "0"
+    try:
+        xu, ru = A.cg(b)
+    finally:
+        os.environ.pop("DSM_CG_FUSED", None)
+    for x, r in ((xf, rf), (xu, ru)):
+        xh = x.cpu().numpy()
+        assert r["status"] == "converged" and abs(r["iters"] - it) <= 1, (r, it)
+        assert oracle.true_relres(p.row_ptr, p.col, p.val, p.b, xh) <= 1.5e-10
+        assert np.linalg.norm(xh - xo) <= 10 * KAPPA[16] * 1e-10 * np.linalg.norm(xo)
+    A.close()
+
+
+def test_cg_fused_maxit_and_breakdown():
+    torch, dev = torch_dev()
+    p = problem("hpcg16")
+    A = make_matrix(p)
+    A.convert("dia")
+    x, res = A.cg(torch.from_numpy(p.b).to(dev), maxit=5)
+    assert res["status"] == "not_converged" and res["iters"] == 5
+    x, res = A.cg(torch.from_numpy(p.b).to(dev), maxit=5, check_every=3)
+    assert res["status"] == "not_converged" and res["iters"] == 5
+    bb = p.b.copy()
+    bb[100] = np.inf
+    x, res = A.cg(torch.from_numpy(bb).to(dev))
+    assert res["status"] == "breakdown"
+    A.close()
