@@ -193,6 +193,22 @@ dsm_status dsm_export(dsm_matrix m, const dsm_export_bufs *bufs, void *stream);
 dsm_status dsm_row_stats(dsm_matrix m, int64_t *out, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Diagonal extraction and update (Section III-D lists both; HPCG's    */
+/* TestCG edits the system matrix's diagonal, Section IV-B).           */
+/* ------------------------------------------------------------------ */
+/* d[i] = A(i, i) for i < min(nrows, ncols), 0 where the structure has no
+ * diagonal entry; d is a device FP64 vector of that length.  Blocking. */
+dsm_status dsm_extract_diagonal(dsm_matrix m, double *d, void *stream);
+
+/* A(i, i) <- d[i] (rounded to the value dtype as in dsm_convert) for every
+ * diagonal entry held by the active format; d is a device FP64 vector of
+ * length min(nrows, ncols).  A non-zero d[i] for an entry the structure
+ * lacks gives DSM_E_INVALID and leaves the matrix unchanged (the structure
+ * is never changed; in DIA/HDC a stored zero there would vanish on the next
+ * conversion, see dsm_convert).  Blocking. */
+dsm_status dsm_update_diagonal(dsm_matrix m, const double *d, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* SpMV (Section III-D "multiply").                                    */
 /* ------------------------------------------------------------------ */
 /* y = A x with x (ncols) and y (nrows) device vectors of `vec_dtype` (F64
@@ -260,10 +276,13 @@ dsm_status dsm_select_cache_clear(dsm_ctx ctx);
 typedef enum {
     DSM_CG_F64 = 0,   /* FP64 vectors, dots and updates; SpMV accumulates in
                          FP64 over the stored values (any value dtype)       */
-    DSM_CG_IR = 1     /* iterative refinement: outer FP64 residual, dots and
+    DSM_CG_IR = 1,    /* iterative refinement: outer FP64 residual, dots and
                          update; inner CG in FP32 vectors with FP32 SpMV
                          accumulation and FP64 dot accumulation (values must
                          be F32 or BF16)                                      */
+    DSM_CG_JACOBI = 2 /* FP64 CG preconditioned with M = diag(A) (the diagonal
+                         from dsm_extract_diagonal; a zero diagonal entry gives
+                         DSM_E_INVALID); stops on ||r|| <= tol ||r0||          */
 } dsm_cg_mode;
 
 typedef struct {

@@ -69,6 +69,9 @@ def lib():
             "orc_row_stats": (None, [_i64, _p, _p]),
             "orc_cg": (_i32, [_i64, _p, _p, _p, _p, _p, _dbl, _i64, _p, _p]),
             "orc_true_relres": (_dbl, [_i64, _p, _p, _p, _p, _p]),
+            "orc_extract_diagonal": (None, [_i64, _i64, _p, _p, _p, _p]),
+            "orc_update_diagonal": (_i64, [_i64, _i64, _p, _p, _p, _p]),
+            "orc_pcg_jacobi": (_i32, [_i64, _p, _p, _p, _p, _p, _dbl, _i64, _p, _p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -331,3 +334,35 @@ def true_relres(row_ptr, col, val, b, x):
     rp, c, v, bb, xx = (_c(row_ptr, np.int32), _c(col, np.int32), _c(val, np.float64),
                         _c(b, np.float64), _c(x, np.float64))
     return lib().orc_true_relres(rp.size - 1, _ptr(rp), _ptr(c), _ptr(v), _ptr(bb), _ptr(xx))
+
+
+def extract_diagonal(nrows, ncols, row_ptr, col, val):
+    rp, c, v = _c(row_ptr, np.int32), _c(col, np.int32), _c(val, np.float64)
+    d = np.empty(min(nrows, ncols), np.float64)
+    lib().orc_extract_diagonal(nrows, ncols, _ptr(rp), _ptr(c), _ptr(v), _ptr(d))
+    return d
+
+
+def update_diagonal(nrows, ncols, row_ptr, col, val, d):
+    """Returns (new values, number of missing entries with d != 0)."""
+    rp, c, dd = _c(row_ptr, np.int32), _c(col, np.int32), _c(d, np.float64)
+    v = np.array(val, dtype=np.float64, copy=True)
+    bad = lib().orc_update_diagonal(nrows, ncols, _ptr(rp), _ptr(c), _ptr(v), _ptr(dd))
+    return v, int(bad)
+
+
+PCG_STATUS = {0: "converged", 1: "not_converged", 2: "breakdown", 3: "zero_diagonal"}
+
+
+def pcg_jacobi(row_ptr, col, val, b, x0=None, tol=1e-10, maxit=None):
+    """Jacobi-preconditioned FP64 CG; returns (x, iters, relres, status)."""
+    rp, c, v, bb = _c(row_ptr, np.int32), _c(col, np.int32), _c(val, np.float64), _c(b, np.float64)
+    n = rp.size - 1
+    x = np.zeros(n, np.float64) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    if maxit is None:
+        maxit = min(10 * n, 20000)
+    it = C.c_int64(0)
+    rr = C.c_double(0.0)
+    st = lib().orc_pcg_jacobi(n, _ptr(rp), _ptr(c), _ptr(v), _ptr(bb), _ptr(x), float(tol), int(maxit),
+                              C.addressof(it), C.addressof(rr))
+    return x, int(it.value), float(rr.value), PCG_STATUS[st]

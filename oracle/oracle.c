@@ -661,3 +661,110 @@ double orc_true_relres(i64 n, const i32 *rp, const i32 *col, const double *val,
     }
     return nb > 0.0 ? sqrt(nr) / sqrt(nb) : sqrt(nr);
 }
+
+/* ------------------------------------------------------------------ */
+/* Diagonal extraction and update (Section III-D lists both; HPCG's    */
+/* TestCG edits the diagonal, Section IV-B).  d[i] = A(i,i) for         */
+/* i < min(nrows, ncols), 0 where the structure has no such entry.      */
+/* ------------------------------------------------------------------ */
+void orc_extract_diagonal(i64 nrows, i64 ncols, const i32 *rp, const i32 *col, const double *val, double *d)
+{
+    i64 nd = nrows < ncols ? nrows : ncols;
+    for (i64 i = 0; i < nd; i++) {
+        d[i] = 0.0;
+        for (i64 k = rp[i]; k < rp[i + 1]; k++)
+            if (col[k] == i) d[i] = val[k];
+    }
+}
+
+/* A(i,i) <- d[i] where the entry exists; returns the number of rows whose
+ * diagonal entry is missing while d[i] != 0 (then nothing is written). */
+i64 orc_update_diagonal(i64 nrows, i64 ncols, const i32 *rp, const i32 *col, double *val, const double *d)
+{
+    i64 nd = nrows < ncols ? nrows : ncols, bad = 0;
+    for (i64 i = 0; i < nd; i++) {
+        int found = 0;
+        for (i64 k = rp[i]; k < rp[i + 1]; k++)
+            if (col[k] == i) found = 1;
+        if (!found && d[i] != 0.0) bad++;
+    }
+    if (bad) return bad;
+    for (i64 i = 0; i < nd; i++)
+        for (i64 k = rp[i]; k < rp[i + 1]; k++)
+            if (col[k] == i) val[k] = d[i];
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Jacobi-preconditioned CG (M = diag(A)), textbook form:               */
+/*   r = b - A x0, z = M^-1 r, p = z, rho = r.z                          */
+/*   loop: q = A p; alpha = rho / p.q; x += alpha p; r -= alpha q;       */
+/*         stop when ||r|| <= tol ||r0||; z = M^-1 r; rho' = r.z;        */
+/*         beta = rho'/rho; p = z + beta p.                              */
+/* Status as orc_cg, plus 3 = a zero diagonal entry.                     */
+/* ------------------------------------------------------------------ */
+int orc_pcg_jacobi(i64 n, const i32 *rp, const i32 *col, const double *val, const double *b, double *x,
+                   double tol, i64 maxit, i64 *iters_out, double *relres_out)
+{
+    size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *dg = (double *)malloc(sz), *r = (double *)malloc(sz), *z = (double *)malloc(sz);
+    double *p = (double *)malloc(sz), *q = (double *)malloc(sz);
+    orc_extract_diagonal(n, n, rp, col, val, dg);
+    int status = 1;
+    i64 it = 0;
+    double relres = 1.0;
+    for (i64 i = 0; i < n; i++)
+        if (dg[i] == 0.0) status = 3;
+    if (status == 3) goto out;
+    spmv_serial(n, rp, col, val, x, q);
+    for (i64 i = 0; i < n; i++) r[i] = b[i] - q[i];
+    for (i64 i = 0; i < n; i++) z[i] = r[i] / dg[i];
+    for (i64 i = 0; i < n; i++) p[i] = z[i];
+    double rho = dot_lr(n, r, z);
+    double nr0 = sqrt(dot_lr(n, r, r));
+    if (nr0 == 0.0) {
+        status = 0;
+        relres = 0.0;
+        goto out;
+    }
+    if (!isfinite(nr0) || !isfinite(rho)) {
+        status = 2;
+        goto out;
+    }
+    while (it < maxit) {
+        spmv_serial(n, rp, col, val, p, q);
+        it++;
+        double pq = dot_lr(n, p, q);
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            status = 2;
+            break;
+        }
+        double alpha = rho / pq;
+        for (i64 i = 0; i < n; i++) x[i] = x[i] + alpha * p[i];
+        for (i64 i = 0; i < n; i++) r[i] = r[i] - alpha * q[i];
+        double nr = sqrt(dot_lr(n, r, r));
+        if (!isfinite(nr)) {
+            status = 2;
+            break;
+        }
+        relres = nr / nr0;
+        if (nr <= tol * nr0) {
+            status = 0;
+            break;
+        }
+        for (i64 i = 0; i < n; i++) z[i] = r[i] / dg[i];
+        double rho1 = dot_lr(n, r, z);
+        double beta = rho1 / rho;
+        for (i64 i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
+        rho = rho1;
+    }
+out:
+    free(dg);
+    free(r);
+    free(z);
+    free(p);
+    free(q);
+    *iters_out = it;
+    *relres_out = relres;
+    return status;
+}

@@ -18,7 +18,7 @@ import numpy as np
 
 from . import _lib as L
 from ._lib import (COO, CSR, DIA, ELL, HYB, HDC, F64, F32, BF16, FORMATS, FORMAT_NAMES, DTYPES, DTYPE_NAMES,
-                   CG_F64, CG_IR)
+                   CG_F64, CG_IR, CG_JACOBI)
 
 __all__ = ["Context", "Matrix", "Server", "DsmError", "lib", "COO", "CSR", "DIA", "ELL", "HYB", "HDC",
            "F64", "F32", "BF16", "FORMATS", "DTYPES", "cg_batched"]
@@ -245,6 +245,22 @@ class Matrix:
         v = list(a)
         return dict(max=v[0], min=v[1], sum=v[2], sumsq=v[3], empty=v[4], hist=np.array(v[5:], np.int64))
 
+    def diagonal(self, out=None, stream=None):
+        """A's diagonal as an FP64 CUDA tensor of length min(nrows, ncols)."""
+        torch = _torch()
+        i = self.info()
+        n = min(i["nrows"], i["ncols"])
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device="cuda")
+        _check(lib().dsm_extract_diagonal(self.h, _dev_ptr(out, n, "out"), _stream(stream)), "dsm_extract_diagonal")
+        return out
+
+    def set_diagonal(self, d, stream=None):
+        """A(i, i) <- d[i] for the diagonal entries the structure holds."""
+        i = self.info()
+        n = min(i["nrows"], i["ncols"])
+        _check(lib().dsm_update_diagonal(self.h, _dev_ptr(d, n, "d"), _stream(stream)), "dsm_update_diagonal")
+
     # ------------------------------------------------------------ compute
     def spmv(self, x, out=None, stream=None):
         torch = _torch()
@@ -301,7 +317,7 @@ def _cg_opts(tol, maxit, mode, inner_tol, check_every, max_outer):
     o = L.CgOpts()
     lib().dsm_cg_opts_default(C.byref(o))
     o.tol, o.maxit = tol, int(maxit)
-    o.mode = {"f64": CG_F64, "ir": CG_IR}[mode] if isinstance(mode, str) else int(mode)
+    o.mode = {"f64": CG_F64, "ir": CG_IR, "jacobi": CG_JACOBI}[mode] if isinstance(mode, str) else int(mode)
     o.inner_tol, o.check_every, o.max_outer = inner_tol, int(check_every), int(max_outer)
     return o
 

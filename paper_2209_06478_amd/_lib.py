@@ -11,7 +11,7 @@ FORMAT_NAMES = {v: k for k, v in FORMATS.items()}
 F64, F32, BF16 = 0, 1, 2
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
 DTYPE_NAMES = {v: k for k, v in DTYPES.items()}
-CG_F64, CG_IR = 0, 1
+CG_F64, CG_IR, CG_JACOBI = 0, 1, 2
 
 OK = 0
 E_INVALID, E_NOMEM, E_INFEASIBLE, E_UNSUPPORTED = -1, -2, -3, -4
@@ -88,6 +88,8 @@ SIGNATURES = {
     "dsm_get_info": (_st, [_p, C.POINTER(Info)]),
     "dsm_export": (_st, [_p, C.POINTER(ExportBufs), _p]),
     "dsm_row_stats": (_st, [_p, C.POINTER(C.c_int64), _p]),
+    "dsm_extract_diagonal": (_st, [_p, _p, _p]),
+    "dsm_update_diagonal": (_st, [_p, _p, _p]),
     "dsm_spmv": (_st, [_p, _p, _p, C.c_int, _p]),
     "dsm_set_variant": (_st, [_p, C.c_int32]),
     "dsm_get_variant": (_st, [_p, C.POINTER(C.c_int32)]),

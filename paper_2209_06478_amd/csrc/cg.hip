@@ -395,10 +395,117 @@ static void enqueue_fused(dsm_matrix m, X *x, X *r, X *pbuf[2], X *q, double *pa
                        part_rr, st, ph);
 }
 
+
+// ---------------------------------------------------------------- Jacobi PCG
+// M = diag(A).  Same loop shape as the plain solver with z = M^-1 r formed on
+// the fly: rho = r.z drives alpha and beta, the stopping test uses ||r||.
+__global__ void k_invert_diag(i64 n, double *d, int *zero) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = d[i];
+    if (v == 0.0 || !isfinite(v)) atomicOr(zero, 1);
+    d[i] = v != 0.0 ? 1.0 / v : 0.0;
+}
+
+__global__ void __launch_bounds__(CGB) k_pcg_init(i64 n, const double *b, const double *q, const double *dinv,
+                                                  double *r, double *p, double *part_rz, double *part_rr) {
+    __shared__ double lds[CGB / WAVE];
+    double rz = 0, rr = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        const double ri = b[i] - q[i];
+        const double zi = ri * dinv[i];
+        r[i] = ri;
+        p[i] = zi;
+        rz += ri * zi;
+        rr += ri * ri;
+    }
+    rz = block_sum(rz, lds);
+    rr = block_sum(rr, lds);
+    if (threadIdx.x == 0) {
+        part_rz[blockIdx.x] = rz;
+        part_rr[blockIdx.x] = rr;
+    }
+}
+
+__global__ void __launch_bounds__(CGB) k_pcg_init_state(const double *part_rz, const double *part_rr, CgState *st,
+                                                        double tol, long long maxit) {
+    __shared__ double lds[CGB / WAVE];
+    const double rz = reduce_partials(part_rz, lds);
+    const double rr = reduce_partials(part_rr, lds);
+    if (threadIdx.x == 0) {
+        st->rho[0] = rz;
+        st->rho[1] = 0;
+        st->nr0 = sqrt(rr);
+        st->pq = 0;
+        st->relres = rr > 0 ? 1.0 : 0.0;
+        st->tol = tol;
+        st->iters = 0;
+        st->maxit = maxit;
+        st->done = rr == 0 ? 1 : ((!isfinite(rr) || !isfinite(rz)) ? 3 : (maxit <= 0 ? 2 : 0));
+    }
+}
+
+__global__ void __launch_bounds__(CGB) k_pcg_update_xr(i64 n, double *x, double *r, const double *p, const double *q,
+                                                       const double *dinv, const double *part_pq, double *part_rz,
+                                                       double *part_rr, CgState *st) {
+    __shared__ double lds[CGB / WAVE];
+    if (wg_done(&st->done)) return;
+    const double pq = reduce_partials(part_pq, lds);
+    const long long k = st->iters;
+    const double rho = st->rho[(k - 1) & 1];
+    if (!(pq > 0) || !isfinite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->pq = pq;
+            st->done = 3;
+        }
+        return;
+    }
+    const double alpha = rho / pq;
+    double rz = 0, rr = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        x[i] = x[i] + alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        rz += ri * (ri * dinv[i]);
+        rr += ri * ri;
+    }
+    rz = block_sum(rz, lds);
+    rr = block_sum(rr, lds);
+    if (threadIdx.x == 0) {
+        part_rz[blockIdx.x] = rz;
+        part_rr[blockIdx.x] = rr;
+        if (blockIdx.x == 0) st->pq = pq;
+    }
+}
+
+__global__ void __launch_bounds__(CGB) k_pcg_update_p(i64 n, const double *r, double *p, const double *dinv,
+                                                      const double *part_rz, const double *part_rr, CgState *st) {
+    __shared__ double lds[CGB / WAVE];
+    if (wg_done(&st->done)) return;
+    const double rho1 = reduce_partials(part_rz, lds);
+    const double nr = sqrt(reduce_partials(part_rr, lds));
+    const long long k = st->iters;
+    const double rho = st->rho[(k - 1) & 1];
+    int done = 0;
+    if (!isfinite(nr) || !isfinite(rho1)) done = 3;
+    else if (nr <= st->tol * st->nr0) done = 1;
+    else if (k >= st->maxit) done = 2;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->relres = st->nr0 > 0 ? nr / st->nr0 : 0.0;
+        st->rho[k & 1] = rho1;
+        if (done) st->done = done;
+    }
+    if (done) return;
+    const double beta = rho1 / rho;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+        p[i] = r[i] * dinv[i] + beta * p[i];
+}
+
 // ================================================================ host side
 struct CgBuffers {
-    // FP64 part (p2: second p buffer of the fused iteration)
-    double *r = nullptr, *p = nullptr, *q = nullptr, *p2 = nullptr;
+    // FP64 part (p2: second p buffer of the fused iteration; dinv: inverse
+    // diagonal of the Jacobi preconditioner)
+    double *r = nullptr, *p = nullptr, *q = nullptr, *p2 = nullptr, *dinv = nullptr, *part_c = nullptr;
     double *part_a = nullptr, *part_b = nullptr, *norms = nullptr;
     CgState *st = nullptr, *st2 = nullptr;
     // FP32 inner part (IR)
@@ -414,7 +521,7 @@ static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 // Workspace bytes a solve of this matrix needs (also used for admission).
 size_t cg_workspace_bytes(i64 n, bool ir) {
     const size_t nn = (size_t)std::max<i64>(n, 1);
-    size_t bytes = 4 * round256(nn * 8) + 2 * round256(partial_slots(n) * 8) + 8 * 256;
+    size_t bytes = 5 * round256(nn * 8) + 3 * round256(partial_slots(n) * 8) + 8 * 256;
     if (ir) bytes += 6 * round256(nn * 4);
     return bytes;
 }
@@ -434,6 +541,8 @@ static CgBuffers cg_buffers(dsm_matrix m, bool ir, Workspace &cgws) {
     B.p2 = (double *)take(n * 8);
     B.part_a = (double *)take(partial_slots(m->nrows) * 8);
     B.part_b = (double *)take(partial_slots(m->nrows) * 8);
+    B.part_c = (double *)take(partial_slots(m->nrows) * 8);
+    B.dinv = (double *)take(n * 8);
     B.norms = (double *)take(64);
     B.st = (CgState *)take(sizeof(CgState));
     B.st2 = (CgState *)take(sizeof(CgState));
@@ -573,6 +682,42 @@ static double true_relres(dsm_matrix m, const double *b, const double *x, CgBuff
     return h[1] > 0 ? h[0] / h[1] : h[0];
 }
 
+void diagonal_op(dsm_matrix m, double *d, int mode, hipStream_t s);
+
+static CgState run_pcg(dsm_matrix m, const double *b, double *x, CgBuffers &B, double tol, long long maxit,
+                       int every, hipStream_t s, Workspace &spws) {
+    const i64 n = m->nrows;
+    diagonal_op(m, B.dinv, 0, s);
+    int *zero = (int *)B.norms;
+    DSM_HIP(hipMemsetAsync(zero, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_invert_diag, dim3(grid_for(n, 256)), dim3(256), 0, s, n, B.dinv, zero);
+    int hz = 0;
+    DSM_HIP(hipMemcpyAsync(&hz, zero, sizeof(int), hipMemcpyDeviceToHost, s));
+    DSM_HIP(hipStreamSynchronize(s));
+    DSM_CHECK(hz == 0, DSM_E_INVALID, "Jacobi preconditioner needs a non-zero finite diagonal");
+    spmv(m, m->P, x, B.q, DSM_F64, m->variant, s, &spws);
+    hipLaunchKernelGGL(k_pcg_init, dim3(CGG), dim3(CGB), 0, s, n, b, B.q, B.dinv, B.r, B.p, B.part_b, B.part_c);
+    hipLaunchKernelGGL(k_pcg_init_state, dim3(1), dim3(CGB), 0, s, B.part_b, B.part_c, B.st, tol, maxit);
+    DSM_HIP(hipGetLastError());
+    CgState h{};
+    long long enq = 0;
+    for (;;) {
+        for (int j = 0; j < every && enq < maxit; j++, enq++) {
+            spmv(m, m->P, B.p, B.q, DSM_F64, m->variant, s, &spws, &B.st->done);
+            hipLaunchKernelGGL((k_cg_dot_pq<double>), dim3(CGG), dim3(CGB), 0, s, n, B.p, B.q, B.part_a, B.st);
+            hipLaunchKernelGGL(k_pcg_update_xr, dim3(CGG), dim3(CGB), 0, s, n, x, B.r, B.p, B.q, B.dinv, B.part_a,
+                               B.part_b, B.part_c, B.st);
+            hipLaunchKernelGGL(k_pcg_update_p, dim3(CGG), dim3(CGB), 0, s, n, B.r, B.p, B.dinv, B.part_b, B.part_c,
+                               B.st);
+        }
+        DSM_HIP(hipGetLastError());
+        DSM_HIP(hipMemcpyAsync(&h, B.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        DSM_HIP(hipStreamSynchronize(s));
+        if (h.done || enq >= maxit) break;
+    }
+    return h;
+}
+
 static int default_check_every(i64 n) { return n < 100000 ? 32 : 8; }
 
 void cg_solve_ws(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o, dsm_cg_result *res, hipStream_t s,
@@ -583,12 +728,22 @@ void cg_solve_ws(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o,
     int every = o.check_every > 0 ? o.check_every : default_check_every(n);
     dsm_cg_result R{};
     const bool ir = o.mode == DSM_CG_IR;
-    DSM_CHECK(o.mode == DSM_CG_F64 || o.mode == DSM_CG_IR, DSM_E_INVALID, "unknown CG mode");
+    DSM_CHECK(o.mode == DSM_CG_F64 || o.mode == DSM_CG_IR || o.mode == DSM_CG_JACOBI, DSM_E_INVALID,
+              "unknown CG mode");
     DSM_CHECK(!ir || m->P.vdt != DSM_F64, DSM_E_UNSUPPORTED,
               "iterative refinement needs F32 or BF16 matrix values (convert with value_dtype)");
     CgBuffers B = cg_buffers(m, ir, cgws);
     if (n == 0) {
         R.status = DSM_OK;
+        *res = R;
+        return;
+    }
+    if (o.mode == DSM_CG_JACOBI) {
+        CgState h = run_pcg(m, b, x, B, o.tol, maxit, every, s, spws);
+        R.iters = h.iters;
+        R.relres = h.relres;
+        R.status = h.done == 1 ? DSM_OK : h.done == 3 ? DSM_E_BREAKDOWN : DSM_E_NOT_CONVERGED;
+        R.relres_true = true_relres(m, b, x, B, s, spws);
         *res = R;
         return;
     }
