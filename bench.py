@@ -231,6 +231,41 @@ def irregular_bench(dsm, ctx, torch, dev):
     return out
 
 
+def split_bench(dsm, ctx, torch, dev, n=104):
+    """One interior rank of a 3x3x3 decomposition with an n^3 local grid:
+    SpMV on the merged rank matrix (CSR, and the best format the selector
+    finds) against the split into a local block and a ghost block, each in
+    its own selected format, added into one y."""
+    import numpy as np
+    import inputs
+    log(f"[bench] local/remote split, rank sub-grid {n}^3")
+    merged, local, ghost = inputs.hpcg27_rank(n, (3, 3, 3), (1, 1, 1))
+    x = torch.from_numpy(inputs.uniform_vector(merged.ncols)).to(dev)
+    y = torch.empty(merged.nrows, dtype=torch.float64, device=dev)
+    M = dsm.Matrix.from_csr(ctx, merged.nrows, merged.ncols, merged.row_ptr, merged.col, merged.val)
+    t_csr = float(np.median(event_times_us(torch, lambda: M.spmv(x, out=y), 50)))
+    rm = M.select(use_cache=False)
+    t_merged = float(np.median(event_times_us(torch, lambda: M.spmv(x, out=y), 50)))
+    L = dsm.Matrix.from_csr(ctx, local.nrows, local.ncols, local.row_ptr, local.col, local.val)
+    G = dsm.Matrix.from_csr(ctx, ghost.nrows, ghost.ncols, ghost.row_ptr, ghost.col, ghost.val)
+    rl, rg = L.select(use_cache=False), G.select(use_cache=False)
+    xl, xg = x[: local.ncols].contiguous(), x[local.ncols:].contiguous()
+
+    def split():
+        L.spmv(xl, out=y)
+        G.spmv_accumulate(xg, y)
+
+    t_split = float(np.median(event_times_us(torch, split, 50)))
+    out = {"rank_rows": merged.nrows, "ghost_cols": ghost.ncols, "nnz": merged.nnz, "ghost_nnz": ghost.nnz,
+           "merged_csr_us": round(t_csr, 2), "merged_selected": rm["chosen"], "merged_selected_us": round(t_merged, 2),
+           "merged_dia_status": rm["status"]["dia"], "split_local": rl["chosen"], "split_ghost": rg["chosen"],
+           "split_us": round(t_split, 2), "split_speedup_vs_merged_csr": round(t_csr / t_split, 3),
+           "split_speedup_vs_merged_selected": round(t_merged / t_split, 3)}
+    for A in (M, L, G):
+        A.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +278,7 @@ def main():
     ap.add_argument("--no-ir", action="store_true", help="skip the mixed-precision CG leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-irregular", action="store_true", help="skip the irregular-matrix selection leg")
+    ap.add_argument("--no-split", action="store_true", help="skip the local/remote split leg")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--format", default=None, help="force a format instead of selecting")
     ap.add_argument("--variant", type=int, default=None, help="kernel variant with --format")
@@ -360,6 +396,7 @@ def main():
 
     irr = None if (args.only_spmv or args.no_irregular) else irregular_bench(dsm, ctx, torch, dev)
     ir = None if (args.only_spmv or args.no_ir) else ir_bench(dsm, ctx, torch, dev)
+    spl = None if (args.only_spmv or args.no_split) else split_bench(dsm, ctx, torch, dev, n=args.n)
     serve = None if (args.only_spmv or args.no_serve) else serving_bench(dsm, ctx, torch, dev,
                                                                           nreq=args.serve_requests)
     cpu = None if args.no_cpu else cpu_baseline(p)
@@ -390,6 +427,7 @@ def main():
         "cg": cg,
         "irregular": irr,
         "ir_cg": ir,
+        "split": spl,
         "serving": serve,
         "cpu_baseline": cpu,
     }

@@ -217,6 +217,11 @@ dsm_status dsm_update_diagonal(dsm_matrix m, const double *d, void *stream);
  * Asynchronous on `stream`. */
 dsm_status dsm_spmv(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, void *stream);
 
+/* y += A x, otherwise as dsm_spmv.  Lets a matrix split into parts held in
+ * different formats - a rank's regular local block and its irregular ghost
+ * block (Section V-A, Fig. 2; Section V-E) - add into one y. */
+dsm_status dsm_spmv_accumulate(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, void *stream);
+
 /* Kernel variant used for SpMV in formats that have several (CSR: 0 =
  * adaptive row blocks, 1..7 = vector kernel with 2^v lanes per row; other
  * formats: 0).  Set by dsm_select or directly. */

@@ -10,6 +10,7 @@ from .rng import splitmix64, u64_stream, uniform, normal
 from .generators import (
     Problem,
     hpcg27,
+    hpcg27_rank,
     aniso7,
     zipf,
     banded,
@@ -22,6 +23,6 @@ from .generators import (
 
 __all__ = [
     "splitmix64", "u64_stream", "uniform", "normal",
-    "Problem", "hpcg27", "aniso7", "zipf", "banded", "banded_spd",
+    "Problem", "hpcg27", "hpcg27_rank", "aniso7", "zipf", "banded", "banded_spd",
     "random_sparse", "uniform_vector", "serving_stream", "ZIPF_EXPONENT",
 ]

@@ -231,6 +231,62 @@ def random_sparse(nrows, ncols, density, seed, max_row=None, empty_rows=0.0):
                    cols.astype(np.int64), vals, {"density": density, "seed": seed})
 
 
+def hpcg27_rank(n, procs=(2, 2, 2), coords=(0, 0, 0)):
+    """One rank's share of an HPCG 27-point problem decomposed over a
+    px x py x pz process grid: the rank owns an n^3 sub-grid at `coords`.
+
+    Returns (merged, local, ghost):
+      merged  rows = the rank's n^3 points; columns = its own points
+              (0 .. n^3-1, same order as hpcg27(n)) followed by the ghost
+              points it couples to (sorted by global index) - the
+              "local system matrix" a distributed HPCG rank holds;
+      local   the square n^3 x n^3 block of couplings inside the sub-grid;
+      ghost   the rectangular n^3 x n_ghost block of couplings to
+              neighbouring sub-grids.
+    merged.b = merged * ones (the global right-hand side of these rows)."""
+    px, py, pz = procs
+    cx, cy, cz = coords
+    gx, gy, gz = n * px, n * py, n * pz
+    N = n ** 3
+    idx = np.arange(N, dtype=np.int64)
+    ix = idx % n + cx * n
+    iy = (idx // n) % n + cy * n
+    iz = idx // (n * n) + cz * n
+    rows_l, gcols_l, vals_l = [], [], []
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                jx, jy, jz = ix + dx, iy + dy, iz + dz
+                ok = (jx >= 0) & (jx < gx) & (jy >= 0) & (jy < gy) & (jz >= 0) & (jz < gz)
+                rows_l.append(idx[ok])
+                gcols_l.append((jx + gx * (jy + gy * jz))[ok])
+                vals_l.append(np.full(int(ok.sum()), 26.0 if (dx, dy, dz) == (0, 0, 0) else -1.0))
+    rows = np.concatenate(rows_l)
+    gcol = np.concatenate(gcols_l)
+    vals = np.concatenate(vals_l)
+    # local column index of an owned point, or -1
+    lx = gcol % gx - cx * n
+    ly = (gcol // gx) % gy - cy * n
+    lz = gcol // (gx * gy) - cz * n
+    own = (lx >= 0) & (lx < n) & (ly >= 0) & (ly < n) & (lz >= 0) & (lz < n)
+    lcol = np.where(own, lx + n * ly + n * n * lz, -1)
+    ghosts = np.unique(gcol[~own])
+    gidx = np.searchsorted(ghosts, gcol[~own])
+    mcol = lcol.copy()
+    mcol[~own] = N + gidx
+    order = np.lexsort((mcol, rows))
+    merged = _finish(f"hpcg27_rank_{n}", N, N + ghosts.size, rows[order], mcol[order], vals[order],
+                     {"n": n, "procs": procs, "coords": coords}, with_b=False)
+    merged.b = np.bincount(rows, weights=vals, minlength=N).astype(np.float64)
+    o = np.lexsort((lcol[own], rows[own]))
+    local = _finish(f"hpcg27_rank_local_{n}", N, N, rows[own][o], lcol[own][o], vals[own][o], {}, with_b=False)
+    g = ~own
+    og = np.lexsort((gidx, rows[g]))
+    ghost = _finish(f"hpcg27_rank_ghost_{n}", N, ghosts.size, rows[g][og], gidx[og], vals[g][og], {}, with_b=False)
+    merged.params["ghost_global"] = ghosts
+    return merged, local, ghost
+
+
 def uniform_vector(n, seed=0x16C0FFEE, stream=7):
     """Seeded uniform[0,1) vector (the SpMV operand of the workloads)."""
     return uniform(seed, stream, np.arange(n, dtype=np.uint64))

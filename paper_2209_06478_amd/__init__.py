@@ -275,6 +275,16 @@ class Matrix:
         _check(lib().dsm_spmv(self.h, xp, yp, vdt, _stream(stream)), "dsm_spmv")
         return out
 
+    def spmv_accumulate(self, x, out, stream=None):
+        """out += A x (device vectors of the same dtype)."""
+        i = self.info()
+        vdt = _vec_dtype(x)
+        if out.dtype != x.dtype:
+            raise TypeError("x and out must have the same dtype")
+        _check(lib().dsm_spmv_accumulate(self.h, _dev_ptr(x, i["ncols"], "x"), _dev_ptr(out, i["nrows"], "out"), vdt,
+                                         _stream(stream)), "dsm_spmv_accumulate")
+        return out
+
     def select(self, mask=ALL_FORMATS, warmup=3, reps=20, use_cache=True, tune_variant=True, vec_dtype="f64",
                value_dtype="f64", max_pad_ratio=16.0, bytes_prefilter=2.0, target=0, stream=None):
         """target 0: time device-wide SpMV; 1: time one-workgroup CG solves."""

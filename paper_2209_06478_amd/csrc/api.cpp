@@ -403,6 +403,17 @@ DSM_API dsm_status dsm_spmv(dsm_matrix m, const void *x, void *y, dsm_dtype vec_
     });
 }
 
+DSM_API dsm_status dsm_spmv_accumulate(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, void *stream) {
+    return guard([&] {
+        check_matrix(m);
+        DSM_CHECK((x || m->ncols == 0) && (y || m->nrows == 0), DSM_E_INVALID, "null vector");
+        DSM_CHECK(x != y || m->nrows == 0, DSM_E_INVALID, "x and y must not alias");
+        hipStream_t s = (hipStream_t)stream;
+        spmv(m, m->P, x, y, vec_dtype, m->variant, s, nullptr, nullptr, true);
+        m->last_stream = s;
+    });
+}
+
 DSM_API dsm_status dsm_set_variant(dsm_matrix m, int32_t variant) {
     return guard([&] {
         check_matrix(m);

@@ -130,9 +130,9 @@ void row_stats(dsm_matrix m, i64 *out, hipStream_t s);
 // y = A x for one payload; vector dtype F64 or F32.  `scratch` holds the
 // COO tile partials (the matrix's own workspace when null).  When `stop`
 // is given, every kernel returns at once if *stop is non-zero (the CG loop's
-// convergence flag).
+// convergence flag).  With `acc` the product is added to y (y += A x).
 void spmv(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant,
-          hipStream_t s, Workspace *scratch = nullptr, const int *stop = nullptr);
+          hipStream_t s, Workspace *scratch = nullptr, const int *stop = nullptr, bool acc = false);
 // Algorithmic bytes one SpMV must move (x read once, y written once).
 double spmv_bytes(const dsm_matrix_s *m, const Payload &P, int vec_dtype);
 // Number of CSR kernel variants (index 0 = adaptive) and of DIA/ELL sweep

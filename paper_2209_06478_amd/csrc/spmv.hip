@@ -353,54 +353,54 @@ static void csr_launch(dsm_matrix m, const Payload &P, const X *x, X *y, int var
 #undef VEC
 }
 
-template <class V, class X, bool XCD, int R, bool NT>
+template <class V, class X, bool ACC, bool XCD, int R, bool NT>
 static void sweep_launch(dsm_matrix m, const Payload &P, const X *x, X *y, hipStream_t s, const int *stop) {
     const i64 n = m->nrows;
     const unsigned g = grid_for(n, SB * R);
     if (P.fmt == DSM_DIA || P.fmt == DSM_HDC)
-        hipLaunchKernelGGL((k_dia<V, X, false, XCD, R, NT>), dim3(g), dim3(SB), 0, s, n, m->ncols, P.ndiag, P.offs,
+        hipLaunchKernelGGL((k_dia<V, X, ACC, XCD, R, NT>), dim3(g), dim3(SB), 0, s, n, m->ncols, P.ndiag, P.offs,
                            (const V *)P.dval, P.pitch, x, y, stop);
     else
-        hipLaunchKernelGGL((k_ell<V, X, false, XCD, R, NT>), dim3(g), dim3(SB), 0, s, n, P.K, P.pitch, P.ecol,
+        hipLaunchKernelGGL((k_ell<V, X, ACC, XCD, R, NT>), dim3(g), dim3(SB), 0, s, n, P.K, P.pitch, P.ecol,
                            (const V *)P.evl, x, y, stop);
 }
 
-template <class V, class X, bool XCD, bool NT>
+template <class V, class X, bool ACC, bool XCD, bool NT>
 static void sweep_r(dsm_matrix m, const Payload &P, const X *x, X *y, int lr, hipStream_t s, const int *stop) {
-    if (lr == 0) sweep_launch<V, X, XCD, 1, NT>(m, P, x, y, s, stop);
-    else if (lr == 1) sweep_launch<V, X, XCD, 2, NT>(m, P, x, y, s, stop);
-    else sweep_launch<V, X, XCD, 4, NT>(m, P, x, y, s, stop);
+    if (lr == 0) sweep_launch<V, X, ACC, XCD, 1, NT>(m, P, x, y, s, stop);
+    else if (lr == 1) sweep_launch<V, X, ACC, XCD, 2, NT>(m, P, x, y, s, stop);
+    else sweep_launch<V, X, ACC, XCD, 4, NT>(m, P, x, y, s, stop);
 }
 
-template <class V, class X>
+template <class V, class X, bool ACC>
 static void sweep(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s, const int *stop) {
     const bool xcd = !(variant & 1), nt = (variant >> 3) & 1;
     const int lr = (variant >> 1) & 3;
-    if (xcd && nt) sweep_r<V, X, true, true>(m, P, x, y, lr, s, stop);
-    else if (xcd) sweep_r<V, X, true, false>(m, P, x, y, lr, s, stop);
-    else if (nt) sweep_r<V, X, false, true>(m, P, x, y, lr, s, stop);
-    else sweep_r<V, X, false, false>(m, P, x, y, lr, s, stop);
+    if (xcd && nt) sweep_r<V, X, ACC, true, true>(m, P, x, y, lr, s, stop);
+    else if (xcd) sweep_r<V, X, ACC, true, false>(m, P, x, y, lr, s, stop);
+    else if (nt) sweep_r<V, X, ACC, false, true>(m, P, x, y, lr, s, stop);
+    else sweep_r<V, X, ACC, false, false>(m, P, x, y, lr, s, stop);
 }
 
-template <class V, class X>
+template <class V, class X, bool ACC>
 static void spmv_typed(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s,
                        Workspace *scratch, const int *stop) {
     const i64 n = m->nrows;
     switch (P.fmt) {
     case DSM_CSR:
-        csr_launch<V, X, false>(m, P, x, y, variant, s, stop);
+        csr_launch<V, X, ACC>(m, P, x, y, variant, s, stop);
         break;
     case DSM_COO:
-        coo_launch<V, X>(m, P.coo_nnz, P.crow, P.ccol, (const V *)P.cval, x, y, false, s, scratch, stop);
+        coo_launch<V, X>(m, P.coo_nnz, P.crow, P.ccol, (const V *)P.cval, x, y, ACC, s, scratch, stop);
         break;
     case DSM_DIA:
     case DSM_HDC:
-        if (n > 0) sweep<V, X>(m, P, x, y, variant, s, stop);
+        if (n > 0) sweep<V, X, ACC>(m, P, x, y, variant, s, stop);
         if (P.fmt == DSM_HDC && P.csr_nnz > 0) csr_launch<V, X, true>(m, P, x, y, 0, s, stop);
         break;
     case DSM_ELL:
     case DSM_HYB:
-        if (n > 0) sweep<V, X>(m, P, x, y, variant, s, stop);
+        if (n > 0) sweep<V, X, ACC>(m, P, x, y, variant, s, stop);
         if (P.fmt == DSM_HYB && P.coo_nnz > 0)
             coo_launch<V, X>(m, P.coo_nnz, P.crow, P.ccol, (const V *)P.cval, x, y, true, s, scratch, stop);
         break;
@@ -411,23 +411,23 @@ static void spmv_typed(dsm_matrix m, const Payload &P, const X *x, X *y, int var
 }
 
 void spmv(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant, hipStream_t s,
-          Workspace *scratch, const int *stop) {
+          Workspace *scratch, const int *stop, bool acc) {
     DSM_CHECK(vdt == DSM_F64 || vdt == DSM_F32, DSM_E_UNSUPPORTED, "spmv: vectors must be F64 or F32");
     if (vdt == DSM_F64) {
         const double *xx = (const double *)x;
         double *yy = (double *)y;
         switch (P.vdt) {
-        case DSM_F64: spmv_typed<double, double>(m, P, xx, yy, variant, s, scratch, stop); break;
-        case DSM_F32: spmv_typed<float, double>(m, P, xx, yy, variant, s, scratch, stop); break;
-        default: spmv_typed<bf16, double>(m, P, xx, yy, variant, s, scratch, stop); break;
+        case DSM_F64: acc ? spmv_typed<double, double, true>(m, P, xx, yy, variant, s, scratch, stop) : spmv_typed<double, double, false>(m, P, xx, yy, variant, s, scratch, stop); break;
+        case DSM_F32: acc ? spmv_typed<float, double, true>(m, P, xx, yy, variant, s, scratch, stop) : spmv_typed<float, double, false>(m, P, xx, yy, variant, s, scratch, stop); break;
+        default: acc ? spmv_typed<bf16, double, true>(m, P, xx, yy, variant, s, scratch, stop) : spmv_typed<bf16, double, false>(m, P, xx, yy, variant, s, scratch, stop); break;
         }
     } else {
         const float *xx = (const float *)x;
         float *yy = (float *)y;
         switch (P.vdt) {
-        case DSM_F64: spmv_typed<double, float>(m, P, xx, yy, variant, s, scratch, stop); break;
-        case DSM_F32: spmv_typed<float, float>(m, P, xx, yy, variant, s, scratch, stop); break;
-        default: spmv_typed<bf16, float>(m, P, xx, yy, variant, s, scratch, stop); break;
+        case DSM_F64: acc ? spmv_typed<double, float, true>(m, P, xx, yy, variant, s, scratch, stop) : spmv_typed<double, float, false>(m, P, xx, yy, variant, s, scratch, stop); break;
+        case DSM_F32: acc ? spmv_typed<float, float, true>(m, P, xx, yy, variant, s, scratch, stop) : spmv_typed<float, float, false>(m, P, xx, yy, variant, s, scratch, stop); break;
+        default: acc ? spmv_typed<bf16, float, true>(m, P, xx, yy, variant, s, scratch, stop) : spmv_typed<bf16, float, false>(m, P, xx, yy, variant, s, scratch, stop); break;
         }
     }
 }
