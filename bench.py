@@ -217,8 +217,17 @@ def irregular_bench(dsm, ctx, torch, dev):
         log(f"[bench] selection on {name}")
         p = gen()
         for vdt in ("f64", "f32"):
+            # the cost model's pick first (no profiling runs; the model has
+            # only learned from the matrices timed before this one)
+            B = dsm.Matrix.from_csr(ctx, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
+            t0 = time.perf_counter()
+            mrep = B.select(use_cache=False, value_dtype=vdt, reps=0)
+            model_ms = (time.perf_counter() - t0) * 1e3
+            B.close()
             A = dsm.Matrix.from_csr(ctx, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
+            t0 = time.perf_counter()
             rep = A.select(use_cache=False, value_dtype=vdt)
+            timed_ms = (time.perf_counter() - t0) * 1e3
             t = {f: us for f, us in rep["median_us"].items() if rep["status"][f] == 0}
             gbps = {f: round(rep["bytes"][f] / (t[f] * 1e-6) / 1e9, 1) for f in t}
             csr_equiv = {f: round(rep["bytes"]["csr"] / (t[f] * 1e-6) / 1e9, 1) for f in t} if "csr" in t else None
@@ -226,7 +235,11 @@ def irregular_bench(dsm, ctx, torch, dev):
                                     "median_us": {f: round(v, 2) for f, v in t.items()}, "gbps": gbps,
                                     "csr_equivalent_gbps": csr_equiv,
                                     "status": rep["status"],
-                                    "speedup_vs_csr": round(t["csr"] / t[rep["chosen"]], 3) if "csr" in t else None}
+                                    "speedup_vs_csr": round(t["csr"] / t[rep["chosen"]], 3) if "csr" in t else None,
+                                    "timed_selection_ms": round(timed_ms, 1),
+                                    "model_choice": mrep["chosen"], "model_selection_ms": round(model_ms, 1),
+                                    "model_choice_slowdown": round(t[mrep["chosen"]] / t[rep["chosen"]], 3)
+                                    if mrep["chosen"] in t else None}
             A.close()
     return out
 

@@ -233,7 +233,13 @@ dsm_status dsm_get_variant(dsm_matrix m, int32_t *variant);
 /* ------------------------------------------------------------------ */
 typedef struct {
     int32_t warmup;        /* untimed runs per candidate (default 3)          */
-    int32_t reps;          /* timed runs per candidate, median kept (def. 20) */
+    int32_t reps;          /* timed runs per candidate, median kept (def. 20);
+                              0 = no profiling runs: pick by the context's
+                              cost model (the bytes each format would move,
+                              computed from the matrix structure on the
+                              device, over per-format bandwidths learned from
+                              the context's earlier timed selections) - the
+                              online selection Section VII leaves open      */
     int32_t use_cache;     /* reuse a previous choice for the same structure  */
     int32_t tune_variant;  /* also time CSR kernel variants (default 1)       */
     dsm_dtype vec_dtype;   /* vector type the SpMVs are timed with            */
@@ -268,7 +274,9 @@ typedef struct {
  * format f) that passes the feasibility prefilter, times SpMV, and leaves
  * the fastest one active (ties within 2% go to fewer bytes).  The original
  * payload is kept until the end, so a failure leaves the handle unchanged.
- * Blocking. */
+ * Every timed selection also updates the context's cost model.  With
+ * reps = 0 the report's median_us holds the model's predictions and only
+ * the chosen format is built.  Blocking. */
 dsm_status dsm_select(dsm_matrix m, uint32_t candidate_mask, const dsm_select_opts *opts,
                       dsm_select_report *report, void *stream);
 

@@ -770,6 +770,80 @@ Payload to_csr(dsm_matrix m, const Payload &src, hipStream_t s) {
     return out;
 }
 
+// ---------------------------------------------------------------- structure features
+// Entries whose column lies within `w` of the row (x gathers that stay in a
+// cache-sized window around the diagonal).
+__global__ void __launch_bounds__(CB) k_near_count(i64 nrows, const i32 *rp, const i32 *col, i64 w,
+                                                   unsigned long long *out) {
+    __shared__ unsigned long long lds[CB / WAVE];
+    unsigned long long c = 0;
+    for_each_entry(nrows, rp, [&](i64 r, i64 e) {
+        const i64 d = (i64)col[e] - r;
+        c += (d <= w && d >= -w) ? 1ull : 0ull;
+    });
+    c = block_sum(c, lds);
+    if (threadIdx.x == 0) atomicAdd(out, c);
+}
+
+// Entries on diagonals whose flag is set (HDC's DIA part).
+__global__ void k_masked_count(i64 span, const i32 *cnt, const i32 *flag, unsigned long long *out) {
+    const i64 d = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d < span && flag[d]) atomicAdd(out, (unsigned long long)cnt[d]);
+}
+
+StructFeatures structure_features(dsm_matrix m, const Payload &C, double theta, i64 window, hipStream_t s) {
+    DSM_CHECK(C.fmt == DSM_CSR, DSM_E_INVALID, "structure_features needs a CSR payload");
+    dsm_ctx ctx = m->ctx;
+    const i64 n = m->nrows, nc = m->ncols, span = n + nc - 1;
+    StructFeatures F{};
+    F.nnz = C.csr_nnz;
+    if (n == 0) return F;
+    F.max_len = max_row_len(ctx, n, C.rp, s);
+    // HYB width from the row-length histogram
+    {
+        Tmp hist(ctx, sizeof(i32) * (size_t)(F.max_len + 2));
+        DSM_HIP(hipMemsetAsync(hist.p, 0, sizeof(i32) * (size_t)(F.max_len + 2), s));
+        hipLaunchKernelGGL(k_len_hist, dim3(grid_for(n, CB)), dim3(CB), 0, s, n, C.rp, hist.as<i32>());
+        i32 *kout = hist.as<i32>() + F.max_len + 1;
+        hipLaunchKernelGGL(k_hyb_width, dim3(1), dim3(64), 0, s, hist.as<i32>(), F.max_len, (n + 2) / 3, kout);
+        Tmp cnt(ctx, sizeof(i32) * (size_t)n), orp(ctx, sizeof(i32) * (size_t)(n + 1));
+        i32 kh = 0;
+        DSM_HIP(hipMemcpyAsync(&kh, kout, sizeof(i32), hipMemcpyDeviceToHost, s));
+        DSM_HIP(hipStreamSynchronize(s));
+        F.hyb_width = kh;
+        hipLaunchKernelGGL(k_overflow_count, dim3(grid_for(n, CB)), dim3(CB), 0, s, n, C.rp, (i64)kh, cnt.as<i32>());
+        DSM_HIP(hipGetLastError());
+        F.hyb_coo = exclusive_scan_i32(ctx, cnt.as<i32>(), orp.as<i32>(), n, s, true);
+    }
+    // diagonals: all of them (DIA) and the well-filled ones (HDC)
+    {
+        Tmp cnt(ctx, sizeof(i32) * (size_t)span), flag(ctx, sizeof(i32) * (size_t)span),
+            acc(ctx, 2 * sizeof(unsigned long long));
+        DSM_HIP(hipMemsetAsync(cnt.p, 0, sizeof(i32) * (size_t)span, s));
+        DSM_HIP(hipMemsetAsync(acc.p, 0, 2 * sizeof(unsigned long long), s));
+        hipLaunchKernelGGL(k_diag_count, dim3(entry_grid(n)), dim3(CB), 0, s, n, C.rp, C.col, cnt.as<i32>());
+        hipLaunchKernelGGL(k_hdc_true, dim3(grid_for(span, CB)), dim3(CB), 0, s, span, n, nc, theta, cnt.as<i32>(),
+                           flag.as<i32>());
+        hipLaunchKernelGGL(k_masked_count, dim3(grid_for(span, CB)), dim3(CB), 0, s, span, cnt.as<i32>(),
+                           flag.as<i32>(), acc.as<unsigned long long>());
+        hipLaunchKernelGGL(k_near_count, dim3(entry_grid(n)), dim3(CB), 0, s, n, C.rp, C.col, window,
+                           acc.as<unsigned long long>() + 1);
+        DSM_HIP(hipGetLastError());
+        Tmp slot(ctx, sizeof(i32) * (size_t)(span + 1));
+        F.hdc_ndiag = exclusive_scan_i32(ctx, flag.as<i32>(), slot.as<i32>(), span, s, true);
+        // every diagonal with at least one entry: mark then count
+        DSM_HIP(hipMemsetAsync(flag.p, 0, sizeof(i32) * (size_t)span, s));
+        hipLaunchKernelGGL(k_diag_mark, dim3(entry_grid(n)), dim3(CB), 0, s, n, C.rp, C.col, flag.as<i32>());
+        F.ndiag = exclusive_scan_i32(ctx, flag.as<i32>(), slot.as<i32>(), span, s, true);
+        unsigned long long h[2];
+        DSM_HIP(hipMemcpyAsync(h, acc.p, sizeof(h), hipMemcpyDeviceToHost, s));
+        DSM_HIP(hipStreamSynchronize(s));
+        F.hdc_dia_nnz = (i64)h[0];
+        F.near = (i64)h[1];
+    }
+    return F;
+}
+
 // ---------------------------------------------------------------- COO ingest
 // Unsorted triplets are ordered by a stable counting sort on rows followed by
 // a per-row insertion sort on columns; the result is the canonical (unique)

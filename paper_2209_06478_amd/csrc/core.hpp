@@ -12,6 +12,11 @@
 #include "common.hpp"
 
 struct dsm_ctx_s {
+    // Effective bandwidth (GB/s) per format of the selection model, learned
+    // from every timed selection on this context; seeded with MI355X values
+    // measured on the HPCG 27-point matrix at 104^3.
+    double model_bw[6] = {2700.0, 3400.0, 5700.0, 3950.0, 3900.0, 5650.0};
+    int model_variant[6] = {0, 0, 4, 0, 0, 0};
     int device = 0;
     size_t budget = 0;                  // 0: no cap
     std::atomic<size_t> in_use{0};
@@ -125,6 +130,14 @@ Payload cast_csr(dsm_matrix m, const Payload &csr, int vdt, hipStream_t s);
 Payload coo_to_csr_payload(dsm_matrix m, const i32 *row, const i32 *col, const double *val,
                            i64 nnz, bool sorted, hipStream_t s);
 void row_stats(dsm_matrix m, i64 *out, hipStream_t s);
+// Structure of a CSR payload that decides every format's size, computed
+// on the device without building the formats: longest row, HYB width and
+// overflow, number of diagonals, HDC's well-filled diagonals and the entries
+// on them, and the entries within `window` of the diagonal.
+struct StructFeatures {
+    i64 nnz = 0, max_len = 0, hyb_width = 0, hyb_coo = 0, ndiag = 0, hdc_ndiag = 0, hdc_dia_nnz = 0, near = 0;
+};
+StructFeatures structure_features(dsm_matrix m, const Payload &C, double theta, i64 window, hipStream_t s);
 
 // ---------------------------------------------------------------- spmv.hip
 // y = A x for one payload; vector dtype F64 or F32.  `scratch` holds the

@@ -55,6 +55,61 @@ static double time_spmv(dsm_matrix m, const Payload &P, int variant, const void 
     return reps ? t[reps / 2] : 0.0;
 }
 
+// ---------------------------------------------------------------- model
+// Bytes a format would move for this structure (as spmv_bytes, from the
+// features alone) plus the extra traffic of x gathers that leave the cache
+// window around the diagonal (one 64-byte sector each, for formats that
+// gather through column indices).
+constexpr i64 NEAR_WINDOW = 1 << 16;
+constexpr double FAR_BYTES = 64.0;
+constexpr double LAUNCH_US = 3.0;
+
+struct Prediction {
+    double bytes[6] = {0, 0, 0, 0, 0, 0};
+    double traffic[6] = {0, 0, 0, 0, 0, 0};
+    int feasible[6] = {0, 0, 0, 0, 0, 0};
+    int launches[6] = {2, 1, 1, 1, 3, 2};
+};
+
+static Prediction predict_bytes(const dsm_matrix_s *m, const StructFeatures &F, int vdt, int vec,
+                                double max_pad_ratio) {
+    Prediction P;
+    const double v = (double)dtype_size(vdt), i = 4.0, X = (double)dtype_size(vec);
+    const double N = (double)m->nrows, nnz = (double)F.nnz, xy = (double)m->ncols * X + N * X;
+    const double far = (double)(F.nnz - F.near);
+    const double ratio = max_pad_ratio > 0 ? max_pad_ratio : 16.0;
+    P.bytes[DSM_COO] = nnz * (v + 2 * i) + xy;
+    P.bytes[DSM_CSR] = nnz * (v + i) + (N + 1) * i + xy;
+    P.bytes[DSM_DIA] = (double)F.ndiag * N * v + (double)F.ndiag * i + xy;
+    P.bytes[DSM_ELL] = (double)F.max_len * N * (v + i) + xy;
+    P.bytes[DSM_HYB] = (double)F.hyb_width * N * (v + i) + (double)F.hyb_coo * (v + 2 * i) + xy;
+    const double rem = nnz - (double)F.hdc_dia_nnz;
+    P.bytes[DSM_HDC] = (double)F.hdc_ndiag * N * v + (double)F.hdc_ndiag * i + rem * (v + i) + (N + 1) * i + xy;
+    for (int f = 0; f < 6; f++) {
+        P.feasible[f] = 1;
+        double fb = far;
+        if (f == DSM_DIA) fb = 0;
+        if (f == DSM_HDC) fb = nnz > 0 ? far * rem / nnz : 0;
+        P.traffic[f] = P.bytes[f] + FAR_BYTES * fb;
+    }
+    if ((double)F.ndiag * N > ratio * std::max(nnz, 1.0)) P.feasible[DSM_DIA] = 0;
+    if ((double)F.max_len * N > ratio * std::max(nnz, 1.0)) P.feasible[DSM_ELL] = 0;
+    return P;
+}
+
+// Feeds one timed selection back into the context's bandwidth table.
+static void learn(dsm_ctx ctx, const Prediction &P, const dsm_select_report &R, const int *best_variant) {
+    std::lock_guard<std::mutex> lk(ctx->cache_mu);
+    for (int f = 0; f < 6; f++) {
+        if (R.status[f] != DSM_OK || R.median_us[f] <= 0) continue;
+        const double t = R.median_us[f] - P.launches[f] * LAUNCH_US;
+        if (t <= 0 || P.traffic[f] <= 0) continue;
+        const double bw = P.traffic[f] / (t * 1e3);  // GB/s
+        ctx->model_bw[f] = 0.5 * ctx->model_bw[f] + 0.5 * bw;
+        if (best_variant[f] >= 0) ctx->model_variant[f] = best_variant[f];
+    }
+}
+
 // preference order for exact ties: CSR, DIA, ELL, HYB, HDC, COO
 static int rank_of(int f) {
     static const int r[6] = {5, 0, 1, 2, 3, 4};
@@ -113,6 +168,76 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
         }
     }
 
+    // structure features of the matrix (through a CSR copy when the active
+    // format is another one); they give the model's exact byte counts
+    StructFeatures F;
+    {
+        Payload tmp;
+        const Payload *C = &m->P;
+        if (m->P.fmt != DSM_CSR) {
+            tmp = to_csr(m, m->P, s);
+            C = &tmp;
+        }
+        try {
+            F = structure_features(m, *C, 0.5, NEAR_WINDOW, s);
+        } catch (...) {
+            tmp.release(ctx);
+            throw;
+        }
+        tmp.release(ctx);
+    }
+    const Prediction PR = predict_bytes(m, F, o.value_dtype, vec, o.max_pad_ratio);
+
+    if (o.reps == 0 && o.target == 0) {
+        // online choice: no profiling runs, the model picks
+        int best = -1;
+        double bt = 0;
+        {
+            std::lock_guard<std::mutex> lk(ctx->cache_mu);
+            for (int f : {DSM_CSR, DSM_DIA, DSM_ELL, DSM_HYB, DSM_HDC, DSM_COO}) {
+                if (!(mask & (1u << f))) continue;
+                R.bytes[f] = PR.bytes[f];
+                if (!PR.feasible[f]) {
+                    R.status[f] = DSM_E_INFEASIBLE;
+                    continue;
+                }
+                R.status[f] = DSM_OK;
+                R.median_us[f] = PR.traffic[f] / (ctx->model_bw[f] * 1e3) + PR.launches[f] * LAUNCH_US;
+                if (best < 0 || R.median_us[f] < bt) {
+                    best = f;
+                    bt = R.median_us[f];
+                }
+            }
+        }
+        DSM_CHECK(best >= 0, DSM_E_INFEASIBLE, "no candidate format is feasible");
+        hipEvent_t c0, c1;
+        DSM_HIP(hipEventCreate(&c0));
+        DSM_HIP(hipEventCreate(&c1));
+        DSM_HIP(hipEventRecord(c0, s));
+        if (!(m->P.fmt == best && m->P.vdt == o.value_dtype)) {
+            Payload np = build_format(m, best, co, s);
+            DSM_HIP(hipStreamSynchronize(s));
+            m->P.release(ctx);
+            m->P = np;
+        }
+        DSM_HIP(hipEventRecord(c1, s));
+        DSM_HIP(hipEventSynchronize(c1));
+        float cms = 0;
+        DSM_HIP(hipEventElapsedTime(&cms, c0, c1));
+        (void)hipEventDestroy(c0);
+        (void)hipEventDestroy(c1);
+        R.convert_us[best] = cms * 1e3;
+        {
+            std::lock_guard<std::mutex> lk(ctx->cache_mu);
+            m->variant = ctx->model_variant[best];
+        }
+        if (m->P.fmt == DSM_COO) m->variant = 0;
+        R.chosen = best;
+        R.chosen_variant = m->variant;
+        if (rep) *rep = R;
+        return;
+    }
+
     const size_t xs = dtype_size(vec);
     void *x = dev_alloc(ctx, xs * (size_t)std::max<i64>(m->ncols, 1));
     void *y = nullptr;
@@ -127,6 +252,7 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
     else hipLaunchKernelGGL(k_fill_value<float>, dim3(gx), dim3(256), 0, s, m->ncols, (float *)x, 1.0f);
 
     Payload best;
+    int best_variant_per_fmt[6] = {-1, -1, -1, -1, -1, -1};
     bool have_best = false, best_is_current = false;
     double best_t = 0, best_bytes = 0, min_bytes = 0;
     int best_f = -1, best_v = 0;
@@ -198,6 +324,7 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
             }
             R.status[f] = DSM_OK;
             R.median_us[f] = tf;
+            best_variant_per_fmt[f] = vf;
             bool better = !have_best;
             if (have_best) {
                 if (tf < best_t * 0.98) better = true;
@@ -230,6 +357,7 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
     }
     cleanup();
     DSM_CHECK(have_best, DSM_E_INFEASIBLE, "no candidate format is feasible");
+    if (o.target == 0) learn(ctx, PR, R, best_variant_per_fmt);
     if (!best_is_current) {
         m->P.release(ctx);
         m->P = best;
@@ -274,7 +402,8 @@ DSM_API dsm_status dsm_select(dsm_matrix m, uint32_t candidate_mask, const dsm_s
         dsm_select_opts o;
         dsm_select_opts_default(&o);
         if (opts) o = *opts;
-        DSM_CHECK(o.reps >= 1 && o.warmup >= 0, DSM_E_INVALID, "reps must be >= 1");
+        DSM_CHECK(o.reps >= 0 && o.warmup >= 0, DSM_E_INVALID, "reps and warmup must be >= 0");
+        DSM_CHECK(o.reps >= 1 || o.target == 0, DSM_E_INVALID, "the batched target needs timed runs");
         DSM_CHECK(o.value_dtype >= DSM_F64 && o.value_dtype <= DSM_BF16, DSM_E_INVALID, "bad value dtype");
         if (o.bytes_prefilter <= 0) o.bytes_prefilter = 2.0;
         select_format(m, candidate_mask, o, report, (hipStream_t)stream);

@@ -94,3 +94,31 @@ def test_select_batched_target():
                                                                           device=dev)])[0]
     assert res["status"] == "converged" and abs(res["iters"] - 27) <= 1
     A.close()
+
+
+@pytest.mark.parametrize("name", ["hpcg104", "zipf50k", "banded20k", "rect_empty"])
+def test_online_model_choice(name):
+    """reps = 0 picks by the context's cost model (no profiling runs): the
+    predicted bytes equal the bytes of the built format, and the model's
+    choice, re-timed, is within 25% of the empirically fastest format."""
+    torch, dev = torch_dev()
+    p = problem(name)
+    c = dsm.Context(0)
+    A = dsm.Matrix.from_csr(c, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
+    emp = A.select(use_cache=False)  # also teaches the context's model
+    B = dsm.Matrix.from_csr(c, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
+    mod = B.select(use_cache=False, reps=0)
+    log(f"[online] {name}: model {mod['chosen']} (pred {mod['median_us']}), timed {emp['chosen']} ({emp['median_us']})")
+    for f, st in emp["status"].items():
+        if st == 0:
+            assert abs(mod["bytes"][f] - emp["bytes"][f]) <= 1e-6 * emp["bytes"][f], f
+    x = torch.from_numpy(x_for(p)).to(dev)
+    y = torch.empty(p.nrows, dtype=torch.float64, device=dev)
+    t_model = median_us(B, x, y)
+    t_emp = median_us(A, x, y)
+    assert t_model <= 1.25 * t_emp + 2.0, (mod["chosen"], t_model, emp["chosen"], t_emp)
+    yref, scale = oracle.spmv_csr_ref(p.row_ptr, p.col, p.val, x_for(p))
+    assert row_scaled_err(B.spmv(x).cpu().numpy(), yref, scale) <= 1e-14
+    A.close()
+    B.close()
+    c.close()
