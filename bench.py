@@ -26,6 +26,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # An entry is removed when its kernel changes.
 PROFILED_TRAFFIC = {
     ("hpcg27_104", "dia", 0): 262312051,
+    ("hpcg27_104", "dia", 4): 261360181,
 }
 
 
@@ -43,6 +44,28 @@ def event_times_us(torch, fn, steps):
         b.record()
     torch.cuda.synchronize()
     return [a.elapsed_time(b) * 1000.0 for a, b in ev]
+
+
+def stream_ceilings(dsm, torch, dev, mib=2048, reps=10):
+    """The library's own streaming kernels over a 2 GiB buffer: read-reduce
+    (a matrix sweep's pattern), copy and write; GB/s from the median launch."""
+    import numpy as np
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    part = torch.empty(dsm.PROBE_PARTIALS, dtype=torch.float64,
+                       device=dev)
+    out = {"mib": mib}
+    for mode, fn, moved in (("read", lambda: dsm.stream_probe("read", part, a), n * 8),
+                            ("copy", lambda: dsm.stream_probe("copy", b, a), 2 * n * 8),
+                            ("write", lambda: dsm.stream_probe("write", b), n * 8)):
+        fn()
+        t = float(np.median(event_times_us(torch, fn, reps)))
+        out[f"{mode}_gbps"] = round(moved / (t * 1e-6) / 1e9, 1)
+    torch.cuda.synchronize()
+    assert abs(float(part.sum()) - n) < 0.5, "read probe sum mismatch"
+    del a, b
+    return out
 
 
 def cpu_baseline(p, budget_s=12.0):
@@ -105,7 +128,7 @@ def ir_bench(dsm, ctx, torch, dev, n=128):
     return out
 
 
-def serving_bench(dsm, ctx, torch, dev, nreq=10000, load=0.8, seed=0x5E4E):
+def serving_bench(dsm, ctx, torch, dev, nreq=10000, load=0.8, seed=0x5E4E, small_rows=40000, poisson=True):
     """Poisson stream of CG solves (tol 1e-8) over a pool of resident
     matrices: 27-point stencils 8^3..96^3 and banded SPD 1k..200k rows."""
     import threading
@@ -145,7 +168,7 @@ def serving_bench(dsm, ctx, torch, dev, nreq=10000, load=0.8, seed=0x5E4E):
     torch.cuda.synchronize()
 
     def run(arrivals):
-        srv = dsm.Server(ctx, slots=128, streams=4, batch_max=256)
+        srv = dsm.Server(ctx, slots=128, streams=4, batch_max=256, small_rows=small_rows)
         tickets = [None] * len(order)
         xs = [None] * len(order)
         t0 = srv.now()
@@ -184,7 +207,7 @@ def serving_bench(dsm, ctx, torch, dev, nreq=10000, load=0.8, seed=0x5E4E):
     rate = sat["solves_per_s"] * load
     gaps = -np.log(1.0 - inputs.uniform(seed, 43, np.arange(nreq, dtype=np.uint64))) / rate
     log(f"[bench] serving: Poisson run at {load} x saturation ({rate:.0f}/s)")
-    open_loop = run(np.cumsum(gaps))
+    open_loop = run(np.cumsum(gaps)) if poisson else None
     # baseline: one request at a time, FP64 CSR device-wide CG, on a sample
     log("[bench] serving: sequential FP64 CSR baseline")
     csr = {}
@@ -203,8 +226,8 @@ def serving_bench(dsm, ctx, torch, dev, nreq=10000, load=0.8, seed=0x5E4E):
            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3)}
     for A in list(csr.values()) + mats:
         A.close()
-    return {"pool": len(pool), "tol": 1e-8, "saturation": sat, "poisson": dict(open_loop, load=load),
-            "sequential_fp64_csr": seq}
+    return {"pool": len(pool), "tol": 1e-8, "small_rows": small_rows, "saturation": sat,
+            "poisson": dict(open_loop, load=load) if open_loop else None, "sequential_fp64_csr": seq}
 
 
 def irregular_bench(dsm, ctx, torch, dev):
@@ -376,6 +399,27 @@ def main():
     value = sel_bytes / (ms_per_step * 1e-3) / 1e9
     achieved = sel_bytes / (avg_us * 1e-6) / 1e9
 
+    # warm (back to back, what CG sees) vs cold (a 1 GiB write evicts L2
+    # and the 256 MB Infinity Cache before each launch) per-launch times
+    ceil = None
+    cache = None
+    if not args.only_spmv:
+        log("[bench] streaming ceilings and cold-cache SpMV")
+        ceil = stream_ceilings(dsm, torch, dev)
+        flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        cold = []
+        for _ in range(args.steps // 4 + 5):
+            dsm.stream_probe("write", flush)
+            cold += event_times_us(torch, spmv, 1)
+        del flush
+        cold = np.array(cold[5:])
+        warm = np.array(ev_us)
+        cache = {m: {"median_us": round(float(np.median(t)), 3), "p90_us": round(float(np.percentile(t, 90)), 3),
+                     "gbps_median": round(sel_bytes / (float(np.median(t)) * 1e-6) / 1e9, 1)}
+                 for m, t in (("warm", warm), ("cold", cold))}
+        cache["cold"]["frac_of_peak"] = round(cache["cold"]["gbps_median"] / HBM_PEAK_GBS, 4)
+        cache["cold"]["frac_of_read_ceiling"] = round(cache["cold"]["gbps_median"] / ceil["read_gbps"], 4)
+
     copy = None
     if args.copy_mb > 0:
         nel = args.copy_mb * (1 << 20) // 8
@@ -437,6 +481,8 @@ def main():
         "speedup_vs_fixed_csr": round(csr_avg / avg_us, 3),
         "select": sel,
         "copy_probe": copy,
+        "stream_ceilings": ceil,
+        "cache_modes": cache,
         "cg": cg,
         "irregular": irr,
         "ir_cg": ir,

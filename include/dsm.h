@@ -222,9 +222,13 @@ dsm_status dsm_spmv(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, v
  * block (Section V-A, Fig. 2; Section V-E) - add into one y. */
 dsm_status dsm_spmv_accumulate(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, void *stream);
 
-/* Kernel variant used for SpMV in formats that have several (CSR: 0 =
- * adaptive row blocks, 1..7 = vector kernel with 2^v lanes per row; other
- * formats: 0).  Set by dsm_select or directly. */
+/* Kernel variant used for SpMV.  CSR (0..7): 0 = adaptive row blocks in
+ * XCD-aware order, 1..6 = vector kernel with 2^v lanes per row, 7 = adaptive
+ * row blocks in launch order.  DIA, ELL and the DIA/ELL parts of HDC/HYB
+ * (0..15): bit 0 = launch order instead of XCD-aware order, bits 1-2 =
+ * log2 of the row groups per thread (1, 2, 4, 4), bit 3 = groups of two
+ * adjacent rows fetched with double-width loads.  COO: 0.  Set by
+ * dsm_select or directly; an out-of-range value gives DSM_E_INVALID. */
 dsm_status dsm_set_variant(dsm_matrix m, int32_t variant);
 dsm_status dsm_get_variant(dsm_matrix m, int32_t *variant);
 
@@ -385,6 +389,22 @@ double dsm_server_now(dsm_server s);
 
 /* Waits for every queued request, stops the scheduler and frees the server. */
 dsm_status dsm_server_destroy(dsm_server s);
+
+/* ------------------------------------------------------------------ */
+/* Streaming probes (measurement only): the practical HBM ceiling that  */
+/* SpMV bandwidth is compared with.                                     */
+/* ------------------------------------------------------------------ */
+#define DSM_PROBE_READ 0      /* read `bytes` of src; dst gets DSM_PROBE_PARTIALS FP64 partial sums */
+#define DSM_PROBE_COPY 1      /* dst[0, bytes) = src[0, bytes) */
+#define DSM_PROBE_WRITE 2     /* dst[0, bytes) = 0 (src unused, may be NULL) */
+#define DSM_PROBE_PARTIALS 4096
+
+/* One streaming kernel over device buffers on `stream` (asynchronous).
+ * `bytes` must be a multiple of 16 and both buffers 16-byte aligned; src and
+ * dst must not overlap.  In read mode dst must hold DSM_PROBE_PARTIALS
+ * doubles (their sum is the sum of src read as FP64 words).  Bad arguments
+ * give DSM_E_INVALID before anything is launched. */
+dsm_status dsm_stream_probe(int32_t mode, const void *src, void *dst, int64_t bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -18,10 +18,10 @@ import numpy as np
 
 from . import _lib as L
 from ._lib import (COO, CSR, DIA, ELL, HYB, HDC, F64, F32, BF16, FORMATS, FORMAT_NAMES, DTYPES, DTYPE_NAMES,
-                   CG_F64, CG_IR, CG_JACOBI)
+                   CG_F64, CG_IR, CG_JACOBI, PROBE_PARTIALS)
 
 __all__ = ["Context", "Matrix", "Server", "DsmError", "lib", "COO", "CSR", "DIA", "ELL", "HYB", "HDC",
-           "F64", "F32", "BF16", "FORMATS", "DTYPES", "cg_batched"]
+           "F64", "F32", "BF16", "FORMATS", "DTYPES", "cg_batched", "stream_probe"]
 
 ALL_FORMATS = (1 << 6) - 1
 
@@ -351,6 +351,24 @@ def cg_batched(mats, bs, xs, tol=1e-10, maxit=0, stream=None):
     R = (L.CgResult * n)()
     _check(lib().dsm_cg_solve_batched(n, H, B, X, O, R, _stream(stream)), "dsm_cg_solve_batched")
     return [_result(r) for r in R]
+
+
+def stream_probe(mode, dst, src=None, stream=None):
+    """One streaming kernel ('read', 'copy' or 'write') over torch device
+    buffers; `read` reduces src into dst (PROBE_PARTIALS float64 partials),
+    `copy` and `write` move dst.numel() * itemsize bytes."""
+    torch = _torch()
+    m = {"read": L.PROBE_READ, "copy": L.PROBE_COPY, "write": L.PROBE_WRITE}[mode]
+    if m == L.PROBE_READ:
+        if dst.dtype != torch.float64 or dst.numel() < L.PROBE_PARTIALS or not dst.is_cuda:
+            raise ValueError(f"read mode needs a float64 CUDA dst of at least {L.PROBE_PARTIALS} elements")
+        nbytes = src.numel() * src.element_size()
+    else:
+        nbytes = dst.numel() * dst.element_size()
+        if m == L.PROBE_COPY and (src is None or src.numel() * src.element_size() < nbytes):
+            raise ValueError("copy needs a src at least as large as dst")
+    sp = C.c_void_p(src.data_ptr()) if src is not None else C.c_void_p(None)
+    _check(lib().dsm_stream_probe(m, sp, C.c_void_p(dst.data_ptr()), nbytes, _stream(stream)), "dsm_stream_probe")
 
 
 class Server:

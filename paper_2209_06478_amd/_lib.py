@@ -108,7 +108,10 @@ SIGNATURES = {
     "dsm_server_wait": (_st, [_p, C.c_uint64, C.POINTER(CgResult), C.POINTER(Timestamps)]),
     "dsm_server_now": (C.c_double, [_p]),
     "dsm_server_destroy": (_st, [_p]),
+    "dsm_stream_probe": (_st, [C.c_int32, _p, _p, C.c_int64, _p]),
 }
+
+PROBE_READ, PROBE_COPY, PROBE_WRITE, PROBE_PARTIALS = 0, 1, 2, 4096
 
 _lib = None
 

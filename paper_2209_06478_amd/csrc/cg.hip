@@ -371,12 +371,12 @@ static void cgf_r(dsm_matrix m, int lr, const X *r, const X *pold, X *pnew, X *q
 template <class V, class X>
 static void cgf_dispatch(dsm_matrix m, const X *r, const X *pold, X *pnew, X *q, double *prr, double *ppq,
                          CgState *st, int ph, hipStream_t s) {
+    // the fused kernel takes the tile order and rows per thread from the
+    // SpMV variant (bits 0-2); it has no paired-row form
     const int v = m->variant;
-    const bool xcd = !(v & 1), nt = (v >> 3) & 1 && m->P.fmt == DSM_DIA;
+    const bool xcd = !(v & 1);
     const int lr = (v >> 1) & 3;
-    if (xcd && nt) cgf_r<V, X, true, true>(m, lr, r, pold, pnew, q, prr, ppq, st, ph, s);
-    else if (xcd) cgf_r<V, X, true, false>(m, lr, r, pold, pnew, q, prr, ppq, st, ph, s);
-    else if (nt) cgf_r<V, X, false, true>(m, lr, r, pold, pnew, q, prr, ppq, st, ph, s);
+    if (xcd) cgf_r<V, X, true, false>(m, lr, r, pold, pnew, q, prr, ppq, st, ph, s);
     else cgf_r<V, X, false, false>(m, lr, r, pold, pnew, q, prr, ppq, st, ph, s);
 }
 

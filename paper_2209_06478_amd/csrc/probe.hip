@@ -1,0 +1,76 @@
+// Streaming probes: the practical HBM ceiling that SpMV kernels are judged
+// against.  A read-reduce (the access pattern of a matrix sweep: read only,
+// a few bytes written), a copy and a write-only fill, each moving 16 B per
+// lane per load/store with four independent accesses in flight per lane.
+#include "core.hpp"
+
+namespace dsm {
+
+constexpr int PB = 256;
+constexpr int PU = 4;
+
+struct alignas(16) d2 {
+    double a, b;
+};
+
+__global__ void __launch_bounds__(PB) k_probe_read(const d2 *__restrict__ src, i64 n, double *__restrict__ part) {
+    const i64 stride = (i64)gridDim.x * PB;
+    i64 i = (i64)blockIdx.x * PB + threadIdx.x;
+    double s = 0.0;
+    for (; i + (PU - 1) * stride < n; i += PU * stride) {
+        d2 v[PU];
+#pragma unroll
+        for (int u = 0; u < PU; u++) v[u] = src[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < PU; u++) s += v[u].a + v[u].b;
+    }
+    for (; i < n; i += stride) s += src[i].a + src[i].b;
+    __shared__ double lds[PB / WAVE];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(PB) k_probe_copy(const d2 *__restrict__ src, d2 *__restrict__ dst, i64 n) {
+    const i64 stride = (i64)gridDim.x * PB;
+    i64 i = (i64)blockIdx.x * PB + threadIdx.x;
+    for (; i + (PU - 1) * stride < n; i += PU * stride) {
+        d2 v[PU];
+#pragma unroll
+        for (int u = 0; u < PU; u++) v[u] = src[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < PU; u++) dst[i + u * stride] = v[u];
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+
+__global__ void __launch_bounds__(PB) k_probe_write(d2 *__restrict__ dst, i64 n) {
+    const i64 stride = (i64)gridDim.x * PB;
+    const d2 z{0.0, 0.0};
+    for (i64 i = (i64)blockIdx.x * PB + threadIdx.x; i < n; i += stride) dst[i] = z;
+}
+
+}  // namespace dsm
+
+using namespace dsm;
+
+DSM_API dsm_status dsm_stream_probe(int32_t mode, const void *src, void *dst, int64_t bytes, void *stream) {
+    return guard([&] {
+        DSM_CHECK(mode >= DSM_PROBE_READ && mode <= DSM_PROBE_WRITE, DSM_E_INVALID, "unknown probe mode");
+        DSM_CHECK(bytes >= 0 && bytes % 16 == 0, DSM_E_INVALID, "bytes must be a non-negative multiple of 16");
+        DSM_CHECK((mode == DSM_PROBE_WRITE || src) && dst, DSM_E_INVALID, "null buffer");
+        DSM_CHECK(((uintptr_t)src % 16) == 0 && ((uintptr_t)dst % 16) == 0, DSM_E_INVALID,
+                  "buffers must be 16-byte aligned");
+        const i64 n = bytes / 16;
+        hipStream_t s = (hipStream_t)stream;
+        const dim3 g(DSM_PROBE_PARTIALS), b(PB);
+        if (mode == DSM_PROBE_READ)
+            hipLaunchKernelGGL(k_probe_read, g, b, 0, s, (const d2 *)src, n, (double *)dst);
+        else if (n == 0)
+            return;
+        else if (mode == DSM_PROBE_COPY)
+            hipLaunchKernelGGL(k_probe_copy, g, b, 0, s, (const d2 *)src, (d2 *)dst, n);
+        else
+            hipLaunchKernelGGL(k_probe_write, g, b, 0, s, (d2 *)dst, n);
+        DSM_HIP(hipGetLastError());
+    });
+}

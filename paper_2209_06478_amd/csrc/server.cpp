@@ -2,10 +2,10 @@
 // HBM budget and run with continuous batching.
 //
 // Each worker thread owns one HIP stream and its own scratch.  A free
-// worker takes, in arrival order, either the next large request (solved by
-// the device-wide CG on its stream) or the run of small requests at the head
-// of the queue (up to batch_max; one persistent launch where each workgroup
-// solves one system).  Requests that arrive while other work is on the GPU
+// worker takes the oldest queued request.  A large one is solved by the
+// device-wide CG on the worker's stream; a small one is batched with every
+// other queued small request that fits (up to batch_max, in arrival order)
+// into one persistent launch where each workgroup solves one system.  Requests that arrive while other work is on the GPU
 // are admitted as soon as a worker, a slot and budget are free, so their
 // kernels overlap with the ones already running.  The footprint charged per
 // request is its matrix payload plus its solver vectors; a request that can
@@ -79,21 +79,24 @@ static void worker_main(dsm_server s) {
             }
             if (s->queue.empty()) break;  // stopping and drained
             const double t = s->now();
-            auto admit = [&](uint64_t id) {
-                auto &r = s->reqs[id];
+            auto admit = [&](std::deque<uint64_t>::iterator it) {
+                auto &r = s->reqs[*it];
                 s->in_flight++;
                 s->bytes_in_flight += r.footprint;
                 r.ts.start_s = t;
-                take.push_back(id);
-                s->queue.pop_front();
+                take.push_back(*it);
+                return s->queue.erase(it);
             };
             small = s->reqs[s->queue.front()].small;
-            admit(s->queue.front());
+            admit(s->queue.begin());
+            // a small head takes every queued small request that fits, in
+            // arrival order, not only the run at the head: in a mixed stream
+            // such runs are short and one-request launches leave the GPU idle
             if (small)
-                while (!s->queue.empty() && (int)take.size() < s->opts.batch_max) {
-                    auto &r = s->reqs[s->queue.front()];
-                    if (!r.small || !s->fits(r)) break;
-                    admit(s->queue.front());
+                for (auto it = s->queue.begin(); it != s->queue.end() && (int)take.size() < s->opts.batch_max;) {
+                    auto &r = s->reqs[*it];
+                    if (r.small && s->fits(r)) it = admit(it);
+                    else ++it;
                 }
         }
         // run outside the lock

@@ -26,6 +26,7 @@ namespace dsm {
 
 constexpr int SB = 256;       // threads per workgroup
 constexpr int RB_T = 1024;    // must match the row-block builder
+constexpr int CU = 4;         // CSR: entries a lane loads before gathering x
 constexpr int COO_E = 4;      // entries per lane in the COO kernel
 constexpr int COO_TE = WAVE * COO_E;
 
@@ -51,13 +52,50 @@ __global__ void __launch_bounds__(SB) k_csr_adaptive(const i32 *__restrict__ blo
     const i64 r0 = blocks[b], r1 = blocks[b + 1];
     const i64 e0 = rp[r0], e1 = rp[r1];
     if (r1 - r0 == 1 && e1 - e0 > RB_T) {  // one long row: whole workgroup
+        // CU entries per lane per pass: all index/value loads are issued
+        // before the dependent x gathers, so a lane keeps CU round trips in
+        // flight instead of one.
         X s = 0;
-        for (i64 e = e0 + tid; e < e1; e += SB) s += widen<X>(val[e]) * x[col[e]];
+        for (i64 base = e0 + tid; base < e1; base += (i64)CU * SB) {
+            i32 c[CU];
+            V v[CU];
+#pragma unroll
+            for (int u = 0; u < CU; u++) {
+                const i64 e = base + (i64)u * SB;
+                if (e < e1) {
+                    c[u] = col[e];
+                    v[u] = val[e];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < CU; u++)
+                if (base + (i64)u * SB < e1) s += widen<X>(v[u]) * x[c[u]];
+        }
         s = block_sum(s, red);
         if (tid == 0) store_y(y, r0, s, ACC);
         return;
     }
-    for (i64 e = e0 + tid; e < e1; e += SB) prod[e - e0] = widen<X>(val[e]) * x[col[e]];
+    {
+        // fewer than 2*RB_T entries: at most 2*RB_T/SB per lane, loaded
+        // together, then gathered together
+        constexpr int PU = 2 * RB_T / SB;
+        const int ne = (int)(e1 - e0);
+        i32 c[PU];
+        V v[PU];
+#pragma unroll
+        for (int u = 0; u < PU; u++) {
+            const int k = tid + u * SB;
+            if (k < ne) {
+                c[u] = col[e0 + k];
+                v[u] = val[e0 + k];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PU; u++) {
+            const int k = tid + u * SB;
+            if (k < ne) prod[k] = widen<X>(v[u]) * x[c[u]];
+        }
+    }
     __syncthreads();
     const int nr = (int)(r1 - r0);
     const int avg = (int)((e1 - e0 + nr - 1) / nr);
@@ -83,7 +121,21 @@ __global__ void __launch_bounds__(SB) k_csr_vector(i64 nrows, const i32 *__restr
     X s = 0;
     if (row < nrows) {
         const i64 a = rp[row], c = rp[row + 1];
-        for (i64 e = a + lane; e < c; e += W) s += widen<X>(val[e]) * x[col[e]];
+        for (i64 base = a + lane; base < c; base += (i64)CU * W) {
+            i32 cc[CU];
+            V v[CU];
+#pragma unroll
+            for (int u = 0; u < CU; u++) {
+                const i64 e = base + (i64)u * W;
+                if (e < c) {
+                    cc[u] = col[e];
+                    v[u] = val[e];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < CU; u++)
+                if (base + (i64)u * W < c) s += widen<X>(v[u]) * x[cc[u]];
+        }
     }
     s = group_sum<W>(s);
     if (row < nrows && lane == 0) store_y(y, row, s, ACC);
@@ -91,62 +143,98 @@ __global__ void __launch_bounds__(SB) k_csr_vector(i64 nrows, const i32 *__restr
 
 // ---------------------------------------------------------------- DIA / ELL
 // Variant bits shared by the DIA and ELL sweeps: bit 0 turns the XCD-aware
-// tile order off, bits 1-2 give log2 of the rows per thread (1, 2, 4; each
-// thread keeps that many independent accumulators, so more loads are in
-// flight), bit 3 streams the matrix values with non-temporal loads (they are
-// read once per SpMV; x and y keep the caches).
-template <class V, class X, bool ACC, bool XCD, int R, bool NT>
+// tile order off, bits 1-2 give log2 of the row groups per thread (1, 2, 4;
+// each group has its own accumulators, so more loads are in flight), bit 3
+// makes a group two adjacent rows whose stored values (and ELL column
+// indices) are fetched with one load of twice the width.
+template <class V>
+struct alignas(2 * sizeof(V)) pair2 {
+    V a, b;
+};
+
+template <class V, class X, bool ACC, bool XCD, int R, bool P2>
 __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, const i32 *__restrict__ offs,
                                             const V *__restrict__ dval, i64 pitch, const X *__restrict__ x,
                                             X *__restrict__ y, const int *__restrict__ stop) {
     if (stop && *stop) return;
+    constexpr int RW = P2 ? 2 : 1;
     const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
-    const i64 i0 = (i64)b * SB * R + threadIdx.x;
-    X s[R];
+    const i64 i0 = (i64)b * SB * R * RW + (i64)threadIdx.x * RW;
+    X s[R][RW];
 #pragma unroll
-    for (int r = 0; r < R; r++) s[r] = 0;
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int w = 0; w < RW; w++) s[r][w] = 0;
     for (i64 k = 0; k < ndiag; k++) {
         const i64 off = offs[k];
         const V *dk = dval + k * pitch;
 #pragma unroll
         for (int r = 0; r < R; r++) {
-            const i64 i = i0 + (i64)r * SB;
+            const i64 i = i0 + (i64)r * SB * RW;
             const i64 j = i + off;
-            if (i < nrows && j >= 0 && j < ncols) s[r] += widen<X>(ld_stream<V, NT>(dk + i)) * x[j];
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const i64 i = i0 + (i64)r * SB;
-        if (i < nrows) store_y(y, i, s[r], ACC);
-    }
-}
-
-template <class V, class X, bool ACC, bool XCD, int R, bool NT>
-__global__ void __launch_bounds__(SB) k_ell(i64 nrows, i64 K, i64 pitch, const i32 *__restrict__ ecol,
-                                            const V *__restrict__ evl, const X *__restrict__ x, X *__restrict__ y,
-                                            const int *__restrict__ stop) {
-    if (stop && *stop) return;
-    const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
-    const i64 i0 = (i64)b * SB * R + threadIdx.x;
-    X s[R];
-#pragma unroll
-    for (int r = 0; r < R; r++) s[r] = 0;
-    for (i64 k = 0; k < K; k++) {
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-            const i64 i = i0 + (i64)r * SB;
-            if (i < nrows) {
-                const i32 c = ld_stream<i32, NT>(ecol + k * pitch + i);
-                if (c >= 0) s[r] += widen<X>(ld_stream<V, NT>(evl + k * pitch + i)) * x[c];
+            if constexpr (P2) {
+                // i is even and the pitch a multiple of 64, so the pair is
+                // aligned; slot i + 1 < pitch always exists (padding is 0)
+                if (i < nrows) {
+                    const pair2<V> v = *(const pair2<V> *)(dk + i);
+                    if (j >= 0 && j < ncols) s[r][0] += widen<X>(v.a) * x[j];
+                    if (i + 1 < nrows && j + 1 >= 0 && j + 1 < ncols) s[r][1] += widen<X>(v.b) * x[j + 1];
+                }
+            } else {
+                if (i < nrows && j >= 0 && j < ncols) s[r][0] += widen<X>(dk[i]) * x[j];
             }
         }
     }
 #pragma unroll
-    for (int r = 0; r < R; r++) {
-        const i64 i = i0 + (i64)r * SB;
-        if (i < nrows) store_y(y, i, s[r], ACC);
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int w = 0; w < RW; w++) {
+            const i64 i = i0 + (i64)r * SB * RW + w;
+            if (i < nrows) store_y(y, i, s[r][w], ACC);
+        }
+}
+
+template <class V, class X, bool ACC, bool XCD, int R, bool P2>
+__global__ void __launch_bounds__(SB) k_ell(i64 nrows, i64 K, i64 pitch, const i32 *__restrict__ ecol,
+                                            const V *__restrict__ evl, const X *__restrict__ x, X *__restrict__ y,
+                                            const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    constexpr int RW = P2 ? 2 : 1;
+    const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const i64 i0 = (i64)b * SB * R * RW + (i64)threadIdx.x * RW;
+    X s[R][RW];
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int w = 0; w < RW; w++) s[r][w] = 0;
+    for (i64 k = 0; k < K; k++) {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const i64 i = i0 + (i64)r * SB * RW;
+            if constexpr (P2) {
+                // rows i (even) and i + 1; slots past nrows are never read
+                if (i + 1 < nrows) {
+                    const pair2<i32> c = *(const pair2<i32> *)(ecol + k * pitch + i);
+                    const pair2<V> v = *(const pair2<V> *)(evl + k * pitch + i);
+                    if (c.a >= 0) s[r][0] += widen<X>(v.a) * x[c.a];
+                    if (c.b >= 0) s[r][1] += widen<X>(v.b) * x[c.b];
+                } else if (i < nrows) {
+                    const i32 c = ecol[k * pitch + i];
+                    if (c >= 0) s[r][0] += widen<X>(evl[k * pitch + i]) * x[c];
+                }
+            } else if (i < nrows) {
+                const i32 c = ecol[k * pitch + i];
+                if (c >= 0) s[r][0] += widen<X>(evl[k * pitch + i]) * x[c];
+            }
+        }
     }
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int w = 0; w < RW; w++) {
+            const i64 i = i0 + (i64)r * SB * RW + w;
+            if (i < nrows) store_y(y, i, s[r][w], ACC);
+        }
 }
 
 // ---------------------------------------------------------------- COO
@@ -353,32 +441,32 @@ static void csr_launch(dsm_matrix m, const Payload &P, const X *x, X *y, int var
 #undef VEC
 }
 
-template <class V, class X, bool ACC, bool XCD, int R, bool NT>
+template <class V, class X, bool ACC, bool XCD, int R, bool P2>
 static void sweep_launch(dsm_matrix m, const Payload &P, const X *x, X *y, hipStream_t s, const int *stop) {
     const i64 n = m->nrows;
-    const unsigned g = grid_for(n, SB * R);
+    const unsigned g = grid_for(n, SB * R * (P2 ? 2 : 1));
     if (P.fmt == DSM_DIA || P.fmt == DSM_HDC)
-        hipLaunchKernelGGL((k_dia<V, X, ACC, XCD, R, NT>), dim3(g), dim3(SB), 0, s, n, m->ncols, P.ndiag, P.offs,
+        hipLaunchKernelGGL((k_dia<V, X, ACC, XCD, R, P2>), dim3(g), dim3(SB), 0, s, n, m->ncols, P.ndiag, P.offs,
                            (const V *)P.dval, P.pitch, x, y, stop);
     else
-        hipLaunchKernelGGL((k_ell<V, X, ACC, XCD, R, NT>), dim3(g), dim3(SB), 0, s, n, P.K, P.pitch, P.ecol,
+        hipLaunchKernelGGL((k_ell<V, X, ACC, XCD, R, P2>), dim3(g), dim3(SB), 0, s, n, P.K, P.pitch, P.ecol,
                            (const V *)P.evl, x, y, stop);
 }
 
-template <class V, class X, bool ACC, bool XCD, bool NT>
+template <class V, class X, bool ACC, bool XCD, bool P2>
 static void sweep_r(dsm_matrix m, const Payload &P, const X *x, X *y, int lr, hipStream_t s, const int *stop) {
-    if (lr == 0) sweep_launch<V, X, ACC, XCD, 1, NT>(m, P, x, y, s, stop);
-    else if (lr == 1) sweep_launch<V, X, ACC, XCD, 2, NT>(m, P, x, y, s, stop);
-    else sweep_launch<V, X, ACC, XCD, 4, NT>(m, P, x, y, s, stop);
+    if (lr == 0) sweep_launch<V, X, ACC, XCD, 1, P2>(m, P, x, y, s, stop);
+    else if (lr == 1) sweep_launch<V, X, ACC, XCD, 2, P2>(m, P, x, y, s, stop);
+    else sweep_launch<V, X, ACC, XCD, 4, P2>(m, P, x, y, s, stop);
 }
 
 template <class V, class X, bool ACC>
 static void sweep(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s, const int *stop) {
-    const bool xcd = !(variant & 1), nt = (variant >> 3) & 1;
+    const bool xcd = !(variant & 1), p2 = (variant >> 3) & 1;
     const int lr = (variant >> 1) & 3;
-    if (xcd && nt) sweep_r<V, X, ACC, true, true>(m, P, x, y, lr, s, stop);
+    if (xcd && p2) sweep_r<V, X, ACC, true, true>(m, P, x, y, lr, s, stop);
     else if (xcd) sweep_r<V, X, ACC, true, false>(m, P, x, y, lr, s, stop);
-    else if (nt) sweep_r<V, X, ACC, false, true>(m, P, x, y, lr, s, stop);
+    else if (p2) sweep_r<V, X, ACC, false, true>(m, P, x, y, lr, s, stop);
     else sweep_r<V, X, ACC, false, false>(m, P, x, y, lr, s, stop);
 }
 
