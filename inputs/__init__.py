@@ -11,6 +11,7 @@ from .generators import (
     Problem,
     hpcg27,
     hpcg27_rank,
+    hpcg27_levels,
     aniso7,
     zipf,
     banded,
@@ -23,6 +24,6 @@ from .generators import (
 
 __all__ = [
     "splitmix64", "u64_stream", "uniform", "normal",
-    "Problem", "hpcg27", "hpcg27_rank", "aniso7", "zipf", "banded", "banded_spd",
+    "Problem", "hpcg27", "hpcg27_rank", "hpcg27_levels", "aniso7", "zipf", "banded", "banded_spd",
     "random_sparse", "uniform_vector", "serving_stream", "ZIPF_EXPONENT",
 ]

@@ -105,6 +105,31 @@ def hpcg27(n):
     return _stencil(n, offs, [-1.0] * 27, 26.0, f"hpcg27_{n}", {"n": n})
 
 
+def hpcg27_levels(n, nlev=4):
+    """HPCG's multigrid hierarchy: the 27-point problem on n^3, (n/2)^3, ...
+    (n divisible by 2^(nlev-1)).  Per level: the Problem, the 8-colour
+    parity colouring colour = (ix & 1) + 2 (iy & 1) + 4 (iz & 1) (rows of
+    one colour share no stencil entry), and, for every level but the
+    coarsest, f2c: the fine row under each row of the next level (coarse
+    point (ix, iy, iz) sits on fine point (2 ix, 2 iy, 2 iz))."""
+    if n % (1 << (nlev - 1)):
+        raise ValueError(f"n={n} is not divisible by 2^{nlev - 1}")
+    levels = []
+    for l in range(nlev):
+        m = n >> l
+        idx = np.arange(m ** 3, dtype=np.int64)
+        ix, iy, iz = idx % m, (idx // m) % m, idx // (m * m)
+        colour = ((ix & 1) + 2 * (iy & 1) + 4 * (iz & 1)).astype(np.int32)
+        lv = {"problem": hpcg27(m), "colour": colour}
+        if l < nlev - 1:
+            c = m // 2
+            cidx = np.arange(c ** 3, dtype=np.int64)
+            cx, cy, cz = cidx % c, (cidx // c) % c, cidx // (c * c)
+            lv["f2c"] = (2 * cx + m * 2 * cy + m * m * 2 * cz).astype(np.int32)
+        levels.append(lv)
+    return levels
+
+
 def aniso7(n, wz=100.0):
     """Dirichlet 7-point Laplacian on n^3 with z-coupling wz."""
     offs = [(0, 0, -1), (0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]

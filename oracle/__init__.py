@@ -72,6 +72,9 @@ def lib():
             "orc_extract_diagonal": (None, [_i64, _i64, _p, _p, _p, _p]),
             "orc_update_diagonal": (_i64, [_i64, _i64, _p, _p, _p, _p]),
             "orc_pcg_jacobi": (_i32, [_i64, _p, _p, _p, _p, _p, _dbl, _i64, _p, _p]),
+            "orc_symgs": (_i64, [_i64, _p, _p, _p, _p, _p, _p]),
+            "orc_mg": (None, [_i32, _p, _p, _p, _p, _p, _p, _p, _p]),
+            "orc_pcg_mg": (_i32, [_i32, _p, _p, _p, _p, _p, _p, _p, _p, _dbl, _i64, _p, _p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -365,4 +368,72 @@ def pcg_jacobi(row_ptr, col, val, b, x0=None, tol=1e-10, maxit=None):
     rr = C.c_double(0.0)
     st = lib().orc_pcg_jacobi(n, _ptr(rp), _ptr(c), _ptr(v), _ptr(bb), _ptr(x), float(tol), int(maxit),
                               C.addressof(it), C.addressof(rr))
+    return x, int(it.value), float(rr.value), PCG_STATUS[st]
+
+
+def symgs(row_ptr, col, val, r, x0, order=None):
+    """One symmetric Gauss-Seidel sweep (forward then backward over `order`,
+    natural order when None) on A x = r from x0; returns (x, bad) where bad
+    counts rows with a zero or missing diagonal (x unchanged then)."""
+    rp, c, v, rr = _c(row_ptr, np.int32), _c(col, np.int32), _c(val, np.float64), _c(r, np.float64)
+    n = rp.size - 1
+    x = np.array(x0, dtype=np.float64, copy=True)
+    o = None if order is None else _c(order, np.int32)
+    bad = lib().orc_symgs(n, _ptr(rp), _ptr(c), _ptr(v), _ptr(rr), _ptr(x), _ptr(o) if o is not None else None)
+    return x, int(bad)
+
+
+class _Levels:
+    """Keeps the per-level arrays alive and exposes them as C pointer arrays.
+    levels: list of dicts with row_ptr, col, val, order (None = natural) and,
+    for every level but the coarsest, f2c (level l+1 row -> level l row)."""
+
+    def __init__(self, levels):
+        self.keep = []
+        L = len(levels)
+        self.nlev = L
+        self.n = np.array([len(lv["row_ptr"]) - 1 for lv in levels], dtype=np.int64)
+        P = C.c_void_p * L
+        arrs = {k: [] for k in ("rp", "col", "val", "ord", "f2c")}
+        for i, lv in enumerate(levels):
+            rp, c, v = _c(lv["row_ptr"], np.int32), _c(lv["col"], np.int32), _c(lv["val"], np.float64)
+            o = lv.get("order")
+            o = np.arange(self.n[i], dtype=np.int32) if o is None else _c(o, np.int32)
+            f = lv.get("f2c") if i < L - 1 else None
+            f = _c(f, np.int32) if f is not None else np.zeros(1, np.int32)
+            self.keep += [rp, c, v, o, f]
+            arrs["rp"].append(rp.ctypes.data)
+            arrs["col"].append(c.ctypes.data if c.size else None)
+            arrs["val"].append(v.ctypes.data if v.size else None)
+            arrs["ord"].append(o.ctypes.data if o.size else None)
+            arrs["f2c"].append(f.ctypes.data)
+        self.ptrs = {k: P(*vs) for k, vs in arrs.items()}
+
+    def args(self):
+        p = self.ptrs
+        return (self.nlev, self.n.ctypes.data, C.addressof(p["rp"]), C.addressof(p["col"]), C.addressof(p["val"]),
+                C.addressof(p["ord"]), C.addressof(p["f2c"]))
+
+
+def mg(levels, r):
+    """One multigrid V-cycle z = M r (from z = 0) over `levels`."""
+    Lv = _Levels(levels)
+    rr = _c(r, np.float64)
+    z = np.empty(Lv.n[0], np.float64)
+    lib().orc_mg(*Lv.args(), _ptr(rr), _ptr(z))
+    return z
+
+
+def pcg_mg(levels, b, x0=None, tol=1e-10, maxit=None):
+    """CG preconditioned by one V-cycle per iteration; returns (x, iters,
+    relres, status)."""
+    Lv = _Levels(levels)
+    bb = _c(b, np.float64)
+    n = int(Lv.n[0])
+    x = np.zeros(n, np.float64) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    if maxit is None:
+        maxit = min(10 * n, 20000)
+    it = C.c_int64(0)
+    rr = C.c_double(0.0)
+    st = lib().orc_pcg_mg(*Lv.args(), _ptr(bb), _ptr(x), float(tol), int(maxit), C.addressof(it), C.addressof(rr))
     return x, int(it.value), float(rr.value), PCG_STATUS[st]
