@@ -302,6 +302,51 @@ def split_bench(dsm, ctx, torch, dev, n=104):
     return out
 
 
+def mg_bench(dsm, ctx, torch, dev, n=104, nlev=4):
+    """HPCG's full PCG on n^3 (four levels n, n/2, n/4, n/8; DIA at every
+    level; multicolour symmetric Gauss-Seidel in a V-cycle) against plain CG
+    on the same DIA matrix, both to 1e-10: iterations, time to solution and
+    time per V-cycle."""
+    import numpy as np
+    import inputs
+    log(f"[bench] multigrid-preconditioned CG on hpcg27_{n} ({nlev} levels)")
+    L = inputs.hpcg27_levels(n, nlev)
+    mats = []
+    for lv in L:
+        p = lv["problem"]
+        A = dsm.Matrix.from_csr(ctx, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
+        A.convert("dia")
+        A.variant = 4
+        mats.append(A)
+    mg = dsm.Multigrid(ctx, mats, [lv["f2c"] for lv in L[:-1]], [lv["colour"] for lv in L])
+    p0 = L[0]["problem"]
+    b = torch.from_numpy(p0.b).to(dev)
+    out = {"levels": [lv["problem"].nrows for lv in L], "format": "dia"}
+    for label, fn in (("pcg_mg", lambda x0: mg.pcg(b, x=x0, tol=1e-10)),
+                      ("cg", lambda x0: mats[0].cg(b, x=x0, tol=1e-10))):
+        ts, res = [], None
+        for _ in range(3):
+            x0 = torch.zeros(p0.nrows, dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, res = fn(x0)
+            ts.append(time.perf_counter() - t0)
+        out[label] = {"ms": round(min(ts) * 1e3, 3), "iters": res["iters"], "status": res["status"],
+                      "relres_true": res["relres_true"],
+                      "ms_per_iter": round(min(ts) * 1e3 / max(res["iters"], 1), 4)}
+    r = torch.from_numpy(inputs.uniform_vector(p0.nrows)).to(dev)
+    z = torch.empty_like(r)
+    for _ in range(3):
+        mg.apply(r, out=z)
+    vt = event_times_us(torch, lambda: mg.apply(r, out=z), 20)
+    out["vcycle_us_median"] = round(float(np.median(vt)), 2)
+    out["speedup_vs_cg"] = round(out["cg"]["ms"] / out["pcg_mg"]["ms"], 3)
+    mg.close()
+    for A in mats:
+        A.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -315,6 +360,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-irregular", action="store_true", help="skip the irregular-matrix selection leg")
     ap.add_argument("--no-split", action="store_true", help="skip the local/remote split leg")
+    ap.add_argument("--no-mg", action="store_true", help="skip the multigrid-preconditioned CG leg")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--format", default=None, help="force a format instead of selecting")
     ap.add_argument("--variant", type=int, default=None, help="kernel variant with --format")
@@ -454,6 +500,7 @@ def main():
     irr = None if (args.only_spmv or args.no_irregular) else irregular_bench(dsm, ctx, torch, dev)
     ir = None if (args.only_spmv or args.no_ir) else ir_bench(dsm, ctx, torch, dev)
     spl = None if (args.only_spmv or args.no_split) else split_bench(dsm, ctx, torch, dev, n=args.n)
+    mgb = None if (args.only_spmv or args.no_mg or args.n % 8) else mg_bench(dsm, ctx, torch, dev, n=args.n)
     serve = None if (args.only_spmv or args.no_serve) else serving_bench(dsm, ctx, torch, dev,
                                                                           nreq=args.serve_requests)
     cpu = None if args.no_cpu else cpu_baseline(p)
@@ -487,6 +534,7 @@ def main():
         "irregular": irr,
         "ir_cg": ir,
         "split": spl,
+        "pcg_mg": mgb,
         "serving": serve,
         "cpu_baseline": cpu,
     }

@@ -391,6 +391,56 @@ double dsm_server_now(dsm_server s);
 dsm_status dsm_server_destroy(dsm_server s);
 
 /* ------------------------------------------------------------------ */
+/* HPCG's preconditioner (Section II-B: PCG with a symmetric Gauss-     */
+/* Seidel smoother inside a multigrid V-cycle; the paper's port turns   */
+/* it off, Section IV-B): one pre- and one post-smoothing sweep per     */
+/* level, restriction by injection of the residual, prolongation by     */
+/* adding the coarse correction back at the injected points, one sweep  */
+/* on the coarsest level.                                                */
+/* ------------------------------------------------------------------ */
+typedef struct dsm_mg_s *dsm_mg;
+
+/* Builds a hierarchy of nlevels (1..8) levels.  levels[0] is the system
+ * matrix, levels[l+1] the next coarser one: square matrices of `ctx` in CSR
+ * or DIA format with FP64 values and a non-zero diagonal.  They are held,
+ * not copied: each must outlive the hierarchy and keep its format and
+ * values array (a later dsm_convert makes the calls below fail with
+ * DSM_E_INVALID).  The smoother reads the diagonal, and for DIA levels all
+ * values (kept in colour order), here: a later dsm_update_diagonal is seen
+ * by the level's SpMV but not by its smoother.
+ * f2c[l] (l < nlevels - 1; host array of levels[l+1]->nrows entries): the
+ * row of level l under each row of level l + 1, all distinct.
+ * colour[l] (host array of levels[l]->nrows entries in [0, 255]): rows of
+ * one colour must not be coupled by a stored off-diagonal entry.  The sweep
+ * updates one colour at a time, ascending forward and descending backward,
+ * which equals a sequential Gauss-Seidel sweep over rows in (colour, row)
+ * order.  Invalid structure (ranges, coupled colours, zero diagonal) gives
+ * DSM_E_INVALID; other formats or dtypes DSM_E_UNSUPPORTED.  Blocking. */
+dsm_status dsm_mg_create(dsm_ctx ctx, int32_t nlevels, const dsm_matrix *levels, const int32_t *const *f2c,
+                         const int32_t *const *colour, void *stream, dsm_mg *out);
+
+/* Waits for the device and frees the hierarchy (not the level matrices). */
+dsm_status dsm_mg_destroy(dsm_mg mg);
+
+/* One symmetric Gauss-Seidel sweep on level `level`: x <- S(x) for
+ * A_level x = r (forward then backward; r, x device FP64 vectors of the
+ * level's size, not aliased).  Asynchronous on `stream`. */
+dsm_status dsm_mg_symgs(dsm_mg mg, int32_t level, const double *r, double *x, void *stream);
+
+/* z = M r: one V-cycle from z = 0 (r, z device FP64 vectors of
+ * levels[0]->nrows, not aliased).  Asynchronous on `stream`; calls that
+ * overlap on one hierarchy race (it owns the coarse-level vectors). */
+dsm_status dsm_mg_apply(dsm_mg mg, const double *r, double *z, void *stream);
+
+/* CG on levels[0] x = b preconditioned by one V-cycle per iteration (HPCG's
+ * solver): b, x device FP64 vectors, x holds x0.  opts: tol, maxit,
+ * check_every as for dsm_cg_solve (mode is ignored).  The result and
+ * return value follow dsm_cg_solve; result->relres is the recursive
+ * ||r||/||r0||, relres_true = ||b - A x|| / ||b||.  Blocking. */
+dsm_status dsm_pcg_mg_solve(dsm_mg mg, const double *b, double *x, const dsm_cg_opts *opts,
+                            dsm_cg_result *result, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Streaming probes (measurement only): the practical HBM ceiling that  */
 /* SpMV bandwidth is compared with.                                     */
 /* ------------------------------------------------------------------ */

@@ -21,7 +21,7 @@ from ._lib import (COO, CSR, DIA, ELL, HYB, HDC, F64, F32, BF16, FORMATS, FORMAT
                    CG_F64, CG_IR, CG_JACOBI, PROBE_PARTIALS)
 
 __all__ = ["Context", "Matrix", "Server", "DsmError", "lib", "COO", "CSR", "DIA", "ELL", "HYB", "HDC",
-           "F64", "F32", "BF16", "FORMATS", "DTYPES", "cg_batched", "stream_probe"]
+           "F64", "F32", "BF16", "FORMATS", "DTYPES", "cg_batched", "stream_probe", "Multigrid"]
 
 ALL_FORMATS = (1 << 6) - 1
 
@@ -411,3 +411,65 @@ class Server:
         if self.h:
             _check(lib().dsm_server_destroy(self.h), "dsm_server_destroy")
             self.h = None
+
+
+class Multigrid:
+    """HPCG's preconditioner over a hierarchy of resident matrices: a
+    symmetric Gauss-Seidel smoother (multicolour) in a multigrid V-cycle,
+    and CG preconditioned by it.  `levels` are Matrix objects (CSR or DIA,
+    FP64), finest first; `f2c[l]` maps level l+1 rows to level l rows;
+    `colours[l]` colours level l's rows (no coupling inside a colour)."""
+
+    def __init__(self, ctx, levels, f2c, colours, stream=None):
+        import numpy as np
+        n = len(levels)
+        self._levels = list(levels)  # the hierarchy holds them
+        self._keep = [np.ascontiguousarray(c, dtype=np.int32) for c in colours]
+        self._keep += [np.ascontiguousarray(f, dtype=np.int32) for f in f2c]
+        cols = (C.c_void_p * n)(*[a.ctypes.data for a in self._keep[:n]])
+        f2 = (C.c_void_p * max(n - 1, 1))(*([a.ctypes.data for a in self._keep[n:]] or [None]))
+        H = (C.c_void_p * n)(*[m.h for m in levels])
+        out = C.c_void_p()
+        _check(lib().dsm_mg_create(ctx.h, n, H, f2, cols, _stream(stream), C.byref(out)), "dsm_mg_create")
+        self.h = out
+        self.n = levels[0].info()["nrows"]
+        self.sizes = [m.info()["nrows"] for m in levels]
+
+    def close(self):
+        if self.h:
+            _check(lib().dsm_mg_destroy(self.h), "dsm_mg_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def symgs(self, level, r, x, stream=None):
+        """One symmetric Gauss-Seidel sweep on `level`, x updated in place."""
+        n = self.sizes[level]
+        _check(lib().dsm_mg_symgs(self.h, int(level), _dev_ptr(r, n, "r"), _dev_ptr(x, n, "x"), _stream(stream)),
+               "dsm_mg_symgs")
+        return x
+
+    def apply(self, r, out=None, stream=None):
+        """z = M r (one V-cycle from zero)."""
+        torch = _torch()
+        z = torch.empty_like(r) if out is None else out
+        _check(lib().dsm_mg_apply(self.h, _dev_ptr(r, self.n, "r"), _dev_ptr(z, self.n, "z"), _stream(stream)),
+               "dsm_mg_apply")
+        return z
+
+    def pcg(self, b, x=None, tol=1e-10, maxit=0, check_every=0, stream=None):
+        """CG preconditioned by one V-cycle per iteration; returns (x, result)."""
+        torch = _torch()
+        if x is None:
+            x = torch.zeros_like(b)
+        o = _cg_opts(tol, maxit, "f64", 1e-4, check_every, 50)
+        R = L.CgResult()
+        st = lib().dsm_pcg_mg_solve(self.h, _dev_ptr(b, self.n, "b"), _dev_ptr(x, self.n, "x"), C.byref(o),
+                                    C.byref(R), _stream(stream))
+        if st not in (L.OK, L.E_NOT_CONVERGED, L.E_BREAKDOWN):
+            _check(st, "dsm_pcg_mg_solve")
+        return x, _result(R)

@@ -109,6 +109,11 @@ SIGNATURES = {
     "dsm_server_now": (C.c_double, [_p]),
     "dsm_server_destroy": (_st, [_p]),
     "dsm_stream_probe": (_st, [C.c_int32, _p, _p, C.c_int64, _p]),
+    "dsm_mg_create": (_st, [_p, C.c_int32, C.POINTER(_p), C.POINTER(_p), C.POINTER(_p), _p, C.POINTER(_p)]),
+    "dsm_mg_destroy": (_st, [_p]),
+    "dsm_mg_symgs": (_st, [_p, C.c_int32, _p, _p, _p]),
+    "dsm_mg_apply": (_st, [_p, _p, _p, _p]),
+    "dsm_pcg_mg_solve": (_st, [_p, _p, _p, C.POINTER(CgOpts), C.POINTER(CgResult), _p]),
 }
 
 PROBE_READ, PROBE_COPY, PROBE_WRITE, PROBE_PARTIALS = 0, 1, 2, 4096

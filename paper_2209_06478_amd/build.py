@@ -16,7 +16,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "scan.hip", "convert.hip", "spmv.hip", "cg.hip", "select.cpp", "batched.hip", "server.cpp", "diag.hip", "probe.hip"]
+SOURCES = ["api.cpp", "scan.hip", "convert.hip", "spmv.hip", "cg.hip", "select.cpp", "batched.hip", "server.cpp", "diag.hip", "probe.hip", "mg.hip"]
 
 FLAGS = [
     "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",

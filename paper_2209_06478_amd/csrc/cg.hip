@@ -23,42 +23,9 @@
 #include <cstdlib>
 #include <vector>
 
-#include "core.hpp"
+#include "cg_common.hpp"
 
 namespace dsm {
-
-constexpr int CGB = 512;    // threads per workgroup in the vector kernels
-constexpr int CGG = 512;    // workgroups in the vector kernels (= partials)
-
-struct CgState {
-    double rho[2];   // r.r before iteration k is rho[(k-1) & 1]
-    double nr0;      // ||r0||
-    double pq;
-    double relres;
-    double tol;
-    long long iters; // SpMVs done inside the loop
-    long long maxit;
-    int done;        // 0 running, 1 converged, 2 iteration limit, 3 breakdown
-    int pad;
-};
-
-// Every workgroup reduces the same `count` partials in the same order.
-__device__ __forceinline__ double reduce_partials(const double *part, double *lds, int count = CGG) {
-    double v = 0;
-    for (int i = threadIdx.x; i < count; i += blockDim.x) v += part[i];
-    return block_sum(v, lds);
-}
-
-// Reads the solve's done flag once per workgroup and shares it through LDS,
-// so every wave of the workgroup takes the same early exit even while
-// workgroup 0 of the same launch is writing the flag (the barriers later in
-// the kernel must see all waves).
-__device__ __forceinline__ bool wg_done(const int *flag) {
-    __shared__ int s_done;
-    if (threadIdx.x == 0) s_done = *(volatile const int *)flag;
-    __syncthreads();
-    return s_done != 0;
-}
 
 template <class X>
 __global__ void __launch_bounds__(CGB) k_cg_init(i64 n, const X *b, const X *q, X *r, X *p, double *part) {
@@ -106,10 +73,11 @@ __global__ void __launch_bounds__(CGB) k_cg_dot_pq(i64 n, const X *p, const X *q
 
 template <class X>
 __global__ void __launch_bounds__(CGB) k_cg_update_xr(i64 n, X *x, X *r, const X *p, const X *q,
-                                                       const double *part_pq, double *part_rr, CgState *st) {
+                                                       const double *part_pq, int npq, double *part_rr,
+                                                       CgState *st) {
     __shared__ double lds[CGB / WAVE];
     if (wg_done(&st->done)) return;
-    const double pq = reduce_partials(part_pq, lds);
+    const double pq = reduce_partials(part_pq, lds, npq);
     const long long k = st->iters;
     const double rho = st->rho[(k - 1) & 1];
     if (!(pq > 0) || !isfinite(pq)) {
@@ -330,10 +298,14 @@ __global__ void __launch_bounds__(CGB) k_cgf_update(i64 n, X *x, X *r, const X *
     }
 }
 
-// Whether the fused two-kernel iteration applies (square DIA/ELL payload).
+// Whether the two-kernel iteration is used (square DIA/ELL payload, asked
+// for with DSM_CG_FUSED=1).  It saves a launch and the p update's pass over
+// r and p, but gathers two vectors per stored entry instead of one; on
+// MI355X the three-kernel loop (SpMV with p.q, x/r update, p update) is
+// faster at the HPCG sizes, so it is the default.
 static bool fused_ok(const dsm_matrix_s *m) {
     const char *e = getenv("DSM_CG_FUSED");
-    if (e && e[0] == '0') return false;
+    if (!(e && e[0] == '1')) return false;
     return m->nrows == m->ncols && (m->P.fmt == DSM_DIA || m->P.fmt == DSM_ELL);
 }
 
@@ -559,20 +531,25 @@ static CgBuffers cg_buffers(dsm_matrix m, bool ir, Workspace &cgws) {
 
 static unsigned vec_grid(i64 n) { return (unsigned)std::max<i64>(1, std::min<i64>(CGG, (n + CGB - 1) / CGB)); }
 
-// One CG iteration: SpMV, p.q, x/r update, p update.  Every kernel checks
-// the state's done flag first, so iterations enqueued past convergence cost
-// only their launches.
+// One CG iteration: SpMV with p.q, x/r update, p update (DIA/ELL sweeps
+// write the p.q partials themselves; other formats take a separate dot
+// kernel).  Every kernel checks the state's done flag first, so iterations
+// enqueued past convergence cost only their launches.
 template <class X>
 static void enqueue_iteration(dsm_matrix m, X *x, X *r, X *p, X *q, double *part_a, double *part_b, CgState *st,
                               int vdt, hipStream_t s, Workspace &spws) {
     const i64 n = m->nrows;
-    spmv(m, m->P, p, q, vdt, m->variant, s, &spws, &st->done);
-    hipLaunchKernelGGL((k_cg_dot_pq<X>), dim3(CGG), dim3(CGB), 0, s, n, p, q, part_a, st);
-    hipLaunchKernelGGL((k_cg_update_xr<X>), dim3(CGG), dim3(CGB), 0, s, n, x, r, p, q, part_a, part_b, st);
+    int npq = spmv_dot(m, m->P, p, q, vdt, m->variant, s, part_a, &st->iters, &st->done);
+    if (npq == 0) {
+        spmv(m, m->P, p, q, vdt, m->variant, s, &spws, &st->done);
+        hipLaunchKernelGGL((k_cg_dot_pq<X>), dim3(CGG), dim3(CGB), 0, s, n, p, q, part_a, st);
+        npq = CGG;
+    }
+    hipLaunchKernelGGL((k_cg_update_xr<X>), dim3(CGG), dim3(CGB), 0, s, n, x, r, p, q, part_a, npq, part_b, st);
     hipLaunchKernelGGL((k_cg_update_p<X>), dim3(CGG), dim3(CGB), 0, s, n, r, p, part_b, st);
 }
 
-static bool graphs_enabled() {
+bool cg_graphs_enabled() {
     const char *e = getenv("DSM_CG_GRAPH");
     return !(e && e[0] == '0');
 }
@@ -603,69 +580,18 @@ static CgState run_cg(dsm_matrix m, const X *b, X *x, X *r, X *p, X *q, X *p2, d
     };
     // the fused loop detects convergence at the start of the next iteration
     const long long cap = maxit + (fused ? 1 : 0);
-    CgState h{};
-    hipStream_t gs = nullptr;
-    hipGraphExec_t exec = nullptr;
-    if (use_graph && graphs_enabled()) {
+    std::string key;
+    if (use_graph) {
         const Payload &P = m->P;
-        char key[512];
-        snprintf(key, sizeof key, "%p|%d|%d|%d|%lld|%lld|%lld|%lld|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%p|%lld|%d",
+        char buf[512];
+        snprintf(buf, sizeof buf, "cg|%p|%d|%d|%d|%lld|%lld|%lld|%lld|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%p|%lld|%d|%p",
                  (void *)m, P.fmt, P.vdt, m->variant, (long long)P.ndiag, (long long)P.K, (long long)P.csr_nnz,
                  (long long)P.coo_nnz, (void *)P.rp, (void *)P.dval, (void *)P.evl, (void *)P.cval, (void *)x,
                  (void *)r, (void *)p, (void *)q, (void *)p2, (void *)part_a, (void *)part_b, vdt, check_every,
-                 spws.p, (long long)n, (int)fused);
-        // private replay stream (default priority, non-blocking)
-        if (!cgws.stream) DSM_HIP(hipStreamCreateWithFlags(&cgws.stream, hipStreamNonBlocking));
-        gs = cgws.stream;
-        // the scratch the SpMV needs is sized by the eager SpMV above
-        if (cgws.graph_key != std::string(key) + "|" + std::to_string((uintptr_t)st)) {
-            if (cgws.graph) (void)hipGraphExecDestroy((hipGraphExec_t)cgws.graph);
-            cgws.graph = nullptr;
-            cgws.graph_key.clear();
-            hipGraph_t g = nullptr;
-            bool ok = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-            if (ok) {
-                // the capture is always closed, also when enqueueing fails
-                try {
-                    for (int j = 0; j < check_every; j++) enqueue(j, gs);
-                } catch (...) {
-                    ok = false;
-                }
-                hipError_t ec = hipStreamEndCapture(gs, &g);
-                ok = ok && ec == hipSuccess && g != nullptr;
-            }
-            hipGraphExec_t ex = nullptr;
-            if (ok) ok = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
-            if (g) (void)hipGraphDestroy(g);
-            (void)hipGetLastError();
-            if (ok) {
-                cgws.graph = ex;
-                cgws.graph_key = std::string(key) + "|" + std::to_string((uintptr_t)st);
-            }
-        }
-        exec = (hipGraphExec_t)cgws.graph;
+                 spws.p, (long long)n, (int)fused, (void *)st);
+        key = buf;
     }
-    if (exec) {
-        DSM_HIP(hipStreamSynchronize(s));  // init work done before the replays
-        long long done_iters = 0;
-        for (;;) {
-            DSM_HIP(hipGraphLaunch(exec, gs));
-            done_iters += check_every;
-            DSM_HIP(hipMemcpyAsync(&h, st, sizeof(CgState), hipMemcpyDeviceToHost, gs));
-            DSM_HIP(hipStreamSynchronize(gs));
-            if (h.done || done_iters >= cap) break;
-        }
-        return h;
-    }
-    long long enq = 0;
-    for (;;) {
-        for (int j = 0; j < check_every && enq < cap; j++, enq++) enqueue(j, s);
-        DSM_HIP(hipGetLastError());
-        DSM_HIP(hipMemcpyAsync(&h, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-        DSM_HIP(hipStreamSynchronize(s));
-        if (h.done || enq >= cap) break;
-    }
-    return h;
+    return run_chunks(cgws, key, use_graph, check_every, cap, st, s, enqueue);
 }
 
 // ||b - A x|| / ||b|| in FP64 on the device (A with its stored values)
@@ -681,8 +607,6 @@ static double true_relres(dsm_matrix m, const double *b, const double *x, CgBuff
     DSM_HIP(hipStreamSynchronize(s));
     return h[1] > 0 ? h[0] / h[1] : h[0];
 }
-
-void diagonal_op(dsm_matrix m, double *d, int mode, hipStream_t s);
 
 static CgState run_pcg(dsm_matrix m, const double *b, double *x, CgBuffers &B, double tol, long long maxit,
                        int every, hipStream_t s, Workspace &spws) {

@@ -12,10 +12,11 @@
 #include "common.hpp"
 
 struct dsm_ctx_s {
-    // Effective bandwidth (GB/s) per format of the selection model, learned
-    // from every timed selection on this context; seeded with MI355X values
-    // measured on the HPCG 27-point matrix at 104^3.
-    double model_bw[6] = {2700.0, 3400.0, 5700.0, 3950.0, 3900.0, 5650.0};
+    // Effective bandwidth (GB/s) of the selection model's kernel classes
+    // (COO, CSR, DIA, ELL sweeps), learned from every timed selection on
+    // this context; seeded with MI355X values measured on the HPCG 27-point
+    // matrix at 104^3.  model_variant: the last best kernel variant per format.
+    double model_bw[4] = {2700.0, 3400.0, 5700.0, 3950.0};
     int model_variant[6] = {0, 0, 4, 0, 0, 0};
     int device = 0;
     size_t budget = 0;                  // 0: no cap
@@ -146,10 +147,18 @@ StructFeatures structure_features(dsm_matrix m, const Payload &C, double theta, 
 // convergence flag).  With `acc` the product is added to y (y += A x).
 void spmv(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant,
           hipStream_t s, Workspace *scratch = nullptr, const int *stop = nullptr, bool acc = false);
+// diag.hip: mode 0 extracts A(i, i) into d (FP64, 0 where absent); mode 1
+// writes d into the diagonal entries the structure holds (blocking).
+void diagonal_op(dsm_matrix m, double *d, int mode, hipStream_t s);
+// Square DIA/ELL only: y = A x plus, per workgroup, the partial of x . y in
+// part[]; *count (when given) is incremented once per launch.  Returns the
+// number of partials written, or 0 (nothing launched) for other payloads.
+int spmv_dot(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant, hipStream_t s,
+             double *part, long long *count, const int *stop);
 // Algorithmic bytes one SpMV must move (x read once, y written once).
 double spmv_bytes(const dsm_matrix_s *m, const Payload &P, int vec_dtype);
 // Number of CSR kernel variants (index 0 = adaptive) and of DIA/ELL sweep
-// variants (tile order x rows per thread x streaming loads).
+// variants (tile order x row groups per thread x paired rows).
 constexpr int CSR_VARIANTS = 8;
 constexpr int SWEEP_VARIANT_COUNT = 16;
 

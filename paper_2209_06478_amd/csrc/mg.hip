@@ -1,0 +1,619 @@
+// HPCG's preconditioner on the device: symmetric Gauss-Seidel smoothing
+// inside a multigrid V-cycle, and CG preconditioned by one V-cycle per
+// iteration (the benchmark's PCG, Section II-B; the paper's port switches
+// it off, Section IV-B).  The cycle follows the HPCG specification: one
+// pre- and one post-smoothing sweep per level, restriction by injection of
+// the residual at the coarse points, prolongation by adding the coarse
+// correction back at those points, one sweep on the coarsest level.
+//
+// Gauss-Seidel is sequential by nature; on the GPU every level carries a
+// colouring in which rows of one colour are not coupled, so a colour's rows
+// are updated together by one launch.  The forward sweep visits the colours
+// in ascending order, the backward sweep in descending order: the result is
+// that of a sequential sweep over rows ordered by (colour, index).  The
+// backward sweep starts at the second-highest colour: re-updating the last
+// colour right after the forward sweep reproduces the same values (its
+// rows see no changed neighbour), so it is skipped.
+//
+// Levels hold CSR or DIA matrices with FP64 values.  CSR rows are reduced
+// by 8 lanes each; DIA rows by one thread sweeping the diagonals in
+// ascending offset (ascending column) order, over a colour-ordered copy of
+// the diagonals made at set-up (the smoother's values are read at set-up:
+// later value updates of a DIA level are not seen by the smoother).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "cg_common.hpp"
+
+namespace dsm {
+
+constexpr int MB = 256;      // threads per workgroup
+constexpr int GSW = 8;       // CSR lanes per row in the smoother
+constexpr int MG_MAX_LEVELS = 8;
+
+}  // namespace dsm
+
+struct dsm_mg_s {
+    struct Level {
+        dsm_matrix A = nullptr;
+        int fmt = 0;
+        const void *payload = nullptr;  // A's value array at create (format guard)
+        int64_t n = 0;
+        std::vector<int64_t> cstart;    // colour c owns rows[cstart[c] .. cstart[c+1])
+        int32_t *rows = nullptr;        // rows grouped by colour, ascending inside a colour
+        double *diag = nullptr;
+        int32_t *f2c = nullptr;         // next level's rows -> rows of this level
+        double *dperm = nullptr;        // DIA: diagonals in colour order (same pitch)
+        double *r = nullptr, *x = nullptr, *ax = nullptr;
+        dsm::Workspace spws;
+    };
+    dsm_ctx ctx = nullptr;
+    std::vector<Level> L;
+    std::vector<std::pair<void *, size_t>> bufs;
+    // PCG vectors and state
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+    double *part_a = nullptr, *part_b = nullptr, *part_c = nullptr;
+    dsm::CgState *st = nullptr;
+    dsm::Workspace gws;
+
+    void *alloc(size_t b) {
+        if (b == 0) b = 16;
+        void *p = dsm::dev_alloc(ctx, b);
+        bufs.push_back({p, b});
+        return p;
+    }
+    void release() {
+        for (auto &l : L) dsm::ws_release(ctx, l.spws);
+        if (gws.graph) (void)hipGraphExecDestroy((hipGraphExec_t)gws.graph);
+        if (gws.stream) (void)hipStreamDestroy(gws.stream);
+        gws.graph = nullptr;
+        gws.stream = nullptr;
+        for (auto &b : bufs) dsm::dev_free(ctx, b.first, b.second);
+        bufs.clear();
+    }
+};
+
+namespace dsm {
+
+// ---------------------------------------------------------------- kernels
+__device__ __forceinline__ bool stopped(const int *stop) { return stop && *(volatile const int *)stop; }
+
+template <int W>
+__global__ void __launch_bounds__(MB) k_symgs_csr(i64 cnt, const i32 *__restrict__ rows, const i32 *__restrict__ rp,
+                                                  const i32 *__restrict__ col, const double *__restrict__ val,
+                                                  const double *__restrict__ diag, const double *__restrict__ r,
+                                                  double *__restrict__ x, const int *stop) {
+    if (stopped(stop)) return;  // the flag is written only by other launches
+    const i64 g = ((i64)blockIdx.x * MB + threadIdx.x) / W;
+    const int lane = threadIdx.x % W;
+    double s = 0;
+    i64 i = 0;
+    if (g < cnt) {
+        i = rows[g];
+        const i64 e1 = rp[i + 1];
+        for (i64 k = rp[i] + lane; k < e1; k += W) {
+            const i32 c = col[k];
+            if (c != i) s += val[k] * x[c];
+        }
+    }
+    s = group_sum<W>(s);
+    if (g < cnt && lane == 0) x[i] = (r[i] - s) / diag[i];
+}
+
+// DIA levels keep a colour-ordered copy of the diagonals: slot t of
+// diagonal k holds A(rows[t], rows[t] + off_k), so a colour's rows are a
+// contiguous, coalesced range of every diagonal (in the natural layout they
+// would be every other slot, wasting half of each line fetched).
+__global__ void __launch_bounds__(MB) k_symgs_dia(i64 t0, i64 cnt, const i32 *__restrict__ rows, i64 n, i64 ndiag,
+                                                  const i32 *__restrict__ offs, const double *__restrict__ dperm,
+                                                  i64 pitch, const double *__restrict__ diag,
+                                                  const double *__restrict__ r, double *__restrict__ x,
+                                                  const int *stop) {
+    if (stopped(stop)) return;
+    const i64 g = (i64)blockIdx.x * MB + threadIdx.x;
+    if (g >= cnt) return;
+    const i64 t = t0 + g;
+    const i64 i = rows[t];
+    double s = 0;
+    for (i64 k = 0; k < ndiag; k++) {
+        const i64 off = offs[k];
+        const i64 j = i + off;
+        if (off != 0 && j >= 0 && j < n) s += dperm[k * pitch + t] * x[j];
+    }
+    x[i] = (r[i] - s) / diag[i];
+}
+
+__global__ void k_dia_colour_order(i64 n, i64 ndiag, const double *__restrict__ dval, i64 pitch,
+                                   const i32 *__restrict__ rows, double *__restrict__ dperm) {
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const i64 i = rows[t];
+    for (i64 k = 0; k < ndiag; k++) dperm[k * pitch + t] = dval[k * pitch + i];
+}
+
+__global__ void k_mg_zero(i64 n, double *x, const int *stop) {
+    if (stopped(stop)) return;
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.0;
+}
+
+// rc = (r - A x) at the coarse points
+__global__ void k_restrict(i64 nc, const i32 *__restrict__ f2c, const double *__restrict__ r,
+                           const double *__restrict__ ax, double *__restrict__ rc, const int *stop) {
+    if (stopped(stop)) return;
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nc) {
+        const i32 f = f2c[i];
+        rc[i] = r[f] - ax[f];
+    }
+}
+
+// x += xc at the coarse points (f2c is injective)
+__global__ void k_prolong(i64 nc, const i32 *__restrict__ f2c, const double *__restrict__ xc, double *__restrict__ x,
+                          const int *stop) {
+    if (stopped(stop)) return;
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nc) {
+        const i32 f = f2c[i];
+        x[f] = x[f] + xc[i];
+    }
+}
+
+// colouring check: a stored off-diagonal entry between two rows of one colour
+__global__ void k_colour_check_csr(i64 n, const i32 *rp, const i32 *col, const i32 *colour, int *bad) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b = 0;
+    for (i64 k = rp[i]; k < rp[i + 1]; k++) {
+        const i32 c = col[k];
+        if (c != i && colour[c] == colour[i]) b = 1;
+    }
+    if (b) atomicAdd(bad, 1);
+}
+
+__global__ void k_colour_check_dia(i64 n, i64 ndiag, const i32 *offs, const double *dval, i64 pitch, const i32 *colour,
+                                   int *bad) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b = 0;
+    for (i64 k = 0; k < ndiag; k++) {
+        const i64 j = i + offs[k];
+        if (offs[k] != 0 && j >= 0 && j < n && dval[k * pitch + i] != 0.0 && colour[j] == colour[i]) b = 1;
+    }
+    if (b) atomicAdd(bad, 1);
+}
+
+__global__ void k_count_bad_diag(i64 n, const double *d, int *bad) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !(d[i] != 0.0 && isfinite(d[i]))) atomicAdd(bad, 1);
+}
+
+// ---- preconditioned CG (z = M r from one V-cycle)
+// r = b - A x0 and partials of r.r
+__global__ void __launch_bounds__(CGB) k_pmg_init(i64 n, const double *b, const double *ax, double *r, double *part) {
+    __shared__ double lds[CGB / WAVE];
+    double acc = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        const double ri = b[i] - ax[i];
+        r[i] = ri;
+        acc += ri * ri;
+    }
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ void __launch_bounds__(CGB) k_pmg_init_state(const double *part, CgState *st, double tol, long long maxit) {
+    __shared__ double lds[CGB / WAVE];
+    const double rr = reduce_partials(part, lds);
+    if (threadIdx.x == 0) {
+        st->rho[0] = st->rho[1] = 0;
+        st->nr0 = sqrt(rr);
+        st->pq = 0;
+        st->relres = rr > 0 ? 1.0 : 0.0;
+        st->tol = tol;
+        st->iters = 0;
+        st->maxit = maxit;
+        st->done = rr == 0 ? 1 : (!isfinite(rr) ? 3 : (maxit <= 0 ? 2 : 0));
+    }
+}
+
+// partials of ||b - ax||^2 and ||b||^2
+__global__ void __launch_bounds__(CGB) k_pmg_norms(i64 n, const double *b, const double *ax, double *part_rr,
+                                                   double *part_bb) {
+    __shared__ double lds[CGB / WAVE];
+    double rr = 0, bb = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        const double ri = b[i] - ax[i];
+        rr += ri * ri;
+        bb += b[i] * b[i];
+    }
+    rr = block_sum(rr, lds);
+    bb = block_sum(bb, lds);
+    if (threadIdx.x == 0) {
+        part_rr[blockIdx.x] = rr;
+        part_bb[blockIdx.x] = bb;
+    }
+}
+
+// partials of r.z
+__global__ void __launch_bounds__(CGB) k_pmg_rz(i64 n, const double *r, const double *z, double *part, CgState *st) {
+    __shared__ double lds[CGB / WAVE];
+    if (wg_done(&st->done)) return;
+    double acc = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+        acc += r[i] * z[i];
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// rho_k = r.z; p = z (first iteration) or z + (rho_k / rho_{k-1}) p.  With
+// k iterations completed, rho_k goes to slot k & 1, rho_{k-1} is in the other.
+__global__ void __launch_bounds__(CGB) k_pmg_update_p(i64 n, const double *z, double *p, const double *part_rz,
+                                                      CgState *st) {
+    __shared__ double lds[CGB / WAVE];
+    if (wg_done(&st->done)) return;
+    const double rz = reduce_partials(part_rz, lds);
+    const long long k = st->iters;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->rho[k & 1] = rz;
+    const bool first = k == 0;
+    const double beta = first ? 0.0 : rz / st->rho[(k & 1) ^ 1];
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+        p[i] = first ? z[i] : z[i] + beta * p[i];
+}
+
+// alpha = rho / p.q; x += alpha p; r -= alpha q; partials of r.r (the SpMV
+// before this kernel counted the iteration: rho is in slot (iters - 1) & 1)
+__global__ void __launch_bounds__(CGB) k_pmg_update_xr(i64 n, double *x, double *r, const double *p, const double *q,
+                                                       const double *part_pq, int npq, double *part_rr, CgState *st) {
+    __shared__ double lds[CGB / WAVE];
+    if (wg_done(&st->done)) return;
+    const double pq = reduce_partials(part_pq, lds, npq);
+    const double rho = st->rho[(st->iters - 1) & 1];
+    if (!(pq > 0) || !isfinite(pq) || !isfinite(rho)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->pq = pq;
+            st->done = 3;
+        }
+        return;
+    }
+    const double alpha = rho / pq;
+    double acc = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        x[i] = x[i] + alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        acc += ri * ri;
+    }
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) {
+        part_rr[blockIdx.x] = acc;
+        if (blockIdx.x == 0) st->pq = pq;
+    }
+}
+
+// convergence test after the update (one workgroup)
+__global__ void __launch_bounds__(CGB) k_pmg_check(const double *part_rr, CgState *st) {
+    __shared__ double lds[CGB / WAVE];
+    if (wg_done(&st->done)) return;
+    const double rr = reduce_partials(part_rr, lds);
+    if (threadIdx.x == 0) {
+        const double nr = sqrt(rr);
+        st->relres = st->nr0 > 0 ? nr / st->nr0 : 0.0;
+        if (!isfinite(rr)) st->done = 3;
+        else if (nr <= st->tol * st->nr0) st->done = 1;
+        else if (st->iters >= st->maxit) st->done = 2;
+    }
+}
+
+template <class X>
+__global__ void __launch_bounds__(CGB) k_pmg_dot_pq(i64 n, const X *p, const X *q, double *part, CgState *st) {
+    __shared__ double lds[CGB / WAVE];
+    if (wg_done(&st->done)) return;
+    double acc = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+        acc += (double)p[i] * (double)q[i];
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = acc;
+        if (blockIdx.x == 0) st->iters += 1;
+    }
+}
+
+// ---------------------------------------------------------------- host side
+static unsigned vgrid(i64 n) { return (unsigned)std::max<i64>(1, std::min<i64>(CGG, (n + CGB - 1) / CGB)); }
+
+static void check_level_format(const dsm_mg_s::Level &l) {
+    DSM_CHECK(l.A->P.fmt == l.fmt && l.A->P.vdt == DSM_F64 &&
+                  (l.fmt == DSM_CSR ? (const void *)l.A->P.val : (const void *)l.A->P.dval) == l.payload,
+              DSM_E_INVALID, "a level matrix changed format or values array since dsm_mg_create");
+}
+
+// One symmetric Gauss-Seidel sweep on level l: x <- S(x) for A_l x = r.
+static void symgs(dsm_mg_s *mg, int l, const double *r, double *x, hipStream_t s, const int *stop) {
+    auto &lv = mg->L[l];
+    const Payload &P = lv.A->P;
+    const int nc = (int)lv.cstart.size() - 1;
+    auto colour = [&](int c) {
+        const i64 c0 = lv.cstart[c], cnt = lv.cstart[c + 1] - c0;
+        if (cnt == 0) return;
+        if (lv.fmt == DSM_CSR)
+            hipLaunchKernelGGL(k_symgs_csr<GSW>, dim3(grid_for(cnt * GSW, MB)), dim3(MB), 0, s, cnt, lv.rows + c0,
+                               P.rp, P.col, (const double *)P.val, lv.diag, r, x, stop);
+        else
+            hipLaunchKernelGGL(k_symgs_dia, dim3(grid_for(cnt, MB)), dim3(MB), 0, s, c0, cnt, lv.rows, lv.n,
+                               P.ndiag, P.offs, lv.dperm, P.pitch, lv.diag, r, x, stop);
+    };
+    for (int c = 0; c < nc; c++) colour(c);
+    for (int c = nc - 2; c >= 0; c--) colour(c);
+    DSM_HIP(hipGetLastError());
+}
+
+// x = M r on level l (x is overwritten; one V-cycle from zero)
+static void vcycle(dsm_mg_s *mg, int l, const double *r, double *x, hipStream_t s, const int *stop) {
+    auto &lv = mg->L[l];
+    hipLaunchKernelGGL(k_mg_zero, dim3(grid_for(lv.n, MB)), dim3(MB), 0, s, lv.n, x, stop);
+    symgs(mg, l, r, x, s, stop);
+    if (l + 1 == (int)mg->L.size()) return;
+    auto &cv = mg->L[l + 1];
+    spmv(lv.A, lv.A->P, x, lv.ax, DSM_F64, lv.A->variant, s, &lv.spws, stop);
+    hipLaunchKernelGGL(k_restrict, dim3(grid_for(cv.n, MB)), dim3(MB), 0, s, cv.n, lv.f2c, r, lv.ax, cv.r, stop);
+    vcycle(mg, l + 1, cv.r, cv.x, s, stop);
+    hipLaunchKernelGGL(k_prolong, dim3(grid_for(cv.n, MB)), dim3(MB), 0, s, cv.n, lv.f2c, cv.x, x, stop);
+    symgs(mg, l, r, x, s, stop);
+    DSM_HIP(hipGetLastError());
+}
+
+static void build_level(dsm_mg_s *mg, int l, dsm_matrix A, const int32_t *colour_h, const int32_t *f2c_h,
+                        int64_t n_next, hipStream_t s) {
+    auto &lv = mg->L[l];
+    lv.A = A;
+    lv.n = A->nrows;
+    lv.fmt = A->P.fmt;
+    lv.payload = lv.fmt == DSM_CSR ? (const void *)A->P.val : (const void *)A->P.dval;
+    const i64 n = lv.n;
+    // colours: host counting sort (stable, so ascending rows inside a colour)
+    DSM_CHECK(colour_h || n == 0, DSM_E_INVALID, "null colour array");
+    int ncol = 0;
+    for (i64 i = 0; i < n; i++) {
+        DSM_CHECK(colour_h[i] >= 0 && colour_h[i] < 256, DSM_E_INVALID, "colours must lie in [0, 255]");
+        ncol = std::max(ncol, colour_h[i] + 1);
+    }
+    lv.cstart.assign(ncol + 1, 0);
+    for (i64 i = 0; i < n; i++) lv.cstart[colour_h[i] + 1]++;
+    for (int c = 0; c < ncol; c++) lv.cstart[c + 1] += lv.cstart[c];
+    std::vector<int32_t> rows((size_t)std::max<i64>(n, 1));
+    {
+        std::vector<int64_t> pos(lv.cstart.begin(), lv.cstart.end() - 1);
+        for (i64 i = 0; i < n; i++) rows[pos[colour_h[i]]++] = (int32_t)i;
+    }
+    lv.rows = (int32_t *)mg->alloc(sizeof(int32_t) * rows.size());
+    lv.diag = (double *)mg->alloc(sizeof(double) * (size_t)std::max<i64>(n, 1));
+    int32_t *col_d = (int32_t *)dev_alloc(mg->ctx, sizeof(int32_t) * (size_t)std::max<i64>(n, 1));
+    int *bad = (int *)dev_alloc(mg->ctx, 2 * sizeof(int));
+    auto cleanup = [&] {
+        (void)hipStreamSynchronize(s);
+        dev_free(mg->ctx, col_d, sizeof(int32_t) * (size_t)std::max<i64>(n, 1));
+        dev_free(mg->ctx, bad, 2 * sizeof(int));
+    };
+    try {
+        DSM_HIP(hipMemcpyAsync(lv.rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice, s));
+        if (n > 0)
+            DSM_HIP(hipMemcpyAsync(col_d, colour_h, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+        DSM_HIP(hipMemsetAsync(bad, 0, 2 * sizeof(int), s));
+        diagonal_op(A, lv.diag, 0, s);
+        if (n > 0) {
+            const Payload &P = A->P;
+            if (lv.fmt == DSM_CSR)
+                hipLaunchKernelGGL(k_colour_check_csr, dim3(grid_for(n, MB)), dim3(MB), 0, s, n, P.rp, P.col, col_d,
+                                   bad);
+            else
+                hipLaunchKernelGGL(k_colour_check_dia, dim3(grid_for(n, MB)), dim3(MB), 0, s, n, P.ndiag, P.offs,
+                                   (const double *)P.dval, P.pitch, col_d, bad);
+            hipLaunchKernelGGL(k_count_bad_diag, dim3(grid_for(n, MB)), dim3(MB), 0, s, n, lv.diag, bad + 1);
+            DSM_HIP(hipGetLastError());
+        }
+        int hb[2] = {0, 0};
+        DSM_HIP(hipMemcpyAsync(hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s));
+        DSM_HIP(hipStreamSynchronize(s));
+        DSM_CHECK(hb[0] == 0, DSM_E_INVALID,
+                  "level " + std::to_string(l) + ": " + std::to_string(hb[0]) +
+                      " rows are coupled to a row of their own colour");
+        DSM_CHECK(hb[1] == 0, DSM_E_INVALID,
+                  "level " + std::to_string(l) + ": " + std::to_string(hb[1]) +
+                      " rows have a zero, missing or non-finite diagonal");
+    } catch (...) {
+        cleanup();
+        throw;
+    }
+    cleanup();
+    if (lv.fmt == DSM_DIA && n > 0) {
+        const Payload &P = A->P;
+        lv.dperm = (double *)mg->alloc(sizeof(double) * (size_t)std::max<i64>(P.ndiag * P.pitch, 1));
+        hipLaunchKernelGGL(k_dia_colour_order, dim3(grid_for(n, MB)), dim3(MB), 0, s, n, P.ndiag,
+                           (const double *)P.dval, P.pitch, lv.rows, lv.dperm);
+        DSM_HIP(hipGetLastError());
+        DSM_HIP(hipStreamSynchronize(s));
+    }
+    lv.ax = (double *)mg->alloc(sizeof(double) * (size_t)std::max<i64>(n, 1));
+    if (l > 0) {
+        lv.r = (double *)mg->alloc(sizeof(double) * (size_t)std::max<i64>(n, 1));
+        lv.x = (double *)mg->alloc(sizeof(double) * (size_t)std::max<i64>(n, 1));
+    }
+    if (f2c_h) {
+        // injective map into this level's rows
+        std::vector<uint8_t> seen((size_t)std::max<i64>(n, 1), 0);
+        for (i64 i = 0; i < n_next; i++) {
+            const int32_t f = f2c_h[i];
+            DSM_CHECK(f >= 0 && f < n && !seen[f], DSM_E_INVALID,
+                      "f2c of level " + std::to_string(l) + " must map coarse rows to distinct rows of the level");
+            seen[f] = 1;
+        }
+        lv.f2c = (int32_t *)mg->alloc(sizeof(int32_t) * (size_t)std::max<i64>(n_next, 1));
+        if (n_next > 0)
+            DSM_HIP(hipMemcpyAsync(lv.f2c, f2c_h, sizeof(int32_t) * (size_t)n_next, hipMemcpyHostToDevice, s));
+        DSM_HIP(hipStreamSynchronize(s));
+    }
+}
+
+static CgState run_pcg_mg(dsm_mg_s *mg, const double *b, double *x, double tol, long long maxit, int every,
+                          hipStream_t s) {
+    auto &l0 = mg->L[0];
+    dsm_matrix A = l0.A;
+    const i64 n = l0.n;
+    CgState *st = mg->st;
+    spmv(A, A->P, x, mg->q, DSM_F64, A->variant, s, &l0.spws);
+    hipLaunchKernelGGL(k_pmg_init, dim3(CGG), dim3(CGB), 0, s, n, b, mg->q, mg->r, mg->part_b);
+    hipLaunchKernelGGL(k_pmg_init_state, dim3(1), dim3(CGB), 0, s, mg->part_b, st, tol, maxit);
+    DSM_HIP(hipGetLastError());
+    const int *stop = &st->done;
+    auto enqueue = [&](int, hipStream_t ss) {
+        vcycle(mg, 0, mg->r, mg->z, ss, stop);
+        hipLaunchKernelGGL(k_pmg_rz, dim3(CGG), dim3(CGB), 0, ss, n, mg->r, mg->z, mg->part_c, st);
+        hipLaunchKernelGGL(k_pmg_update_p, dim3(CGG), dim3(CGB), 0, ss, n, mg->z, mg->p, mg->part_c, st);
+        int npq = spmv_dot(A, A->P, mg->p, mg->q, DSM_F64, A->variant, ss, mg->part_a, &st->iters, stop);
+        if (npq == 0) {
+            spmv(A, A->P, mg->p, mg->q, DSM_F64, A->variant, ss, &l0.spws, stop);
+            hipLaunchKernelGGL(k_pmg_dot_pq<double>, dim3(CGG), dim3(CGB), 0, ss, n, mg->p, mg->q, mg->part_a, st);
+            npq = CGG;
+        }
+        hipLaunchKernelGGL(k_pmg_update_xr, dim3(CGG), dim3(CGB), 0, ss, n, x, mg->r, mg->p, mg->q, mg->part_a,
+                           npq, mg->part_b, st);
+        hipLaunchKernelGGL(k_pmg_check, dim3(1), dim3(CGB), 0, ss, mg->part_b, st);
+        DSM_HIP(hipGetLastError());
+    };
+    char key[256];
+    snprintf(key, sizeof key, "pmg|%p|%p|%p|%d|%d", (void *)b, (void *)x, (void *)mg, A->variant, every);
+    return run_chunks(mg->gws, key, true, every, maxit, st, s, enqueue);
+}
+
+}  // namespace dsm
+
+using namespace dsm;
+
+static size_t pcg_partials(int64_t n) { return (size_t)std::max<int64_t>(CGG, n / 256 + 2); }
+
+DSM_API dsm_status dsm_mg_create(dsm_ctx ctx, int32_t nlevels, const dsm_matrix *levels, const int32_t *const *f2c,
+                                 const int32_t *const *colour, void *stream, dsm_mg *out) {
+    return guard([&] {
+        DSM_CHECK(ctx && levels && colour && out, DSM_E_INVALID, "null argument");
+        DSM_CHECK(nlevels >= 1 && nlevels <= MG_MAX_LEVELS, DSM_E_INVALID, "nlevels must be in [1, 8]");
+        DSM_CHECK(nlevels == 1 || f2c, DSM_E_INVALID, "f2c is needed with more than one level");
+        for (int l = 0; l < nlevels; l++) {
+            dsm_matrix A = levels[l];
+            DSM_CHECK(A && A->ctx == ctx, DSM_E_INVALID, "null level matrix or one of another context");
+            DSM_CHECK(A->nrows == A->ncols, DSM_E_UNSUPPORTED, "level matrices must be square");
+            DSM_CHECK((A->P.fmt == DSM_CSR || A->P.fmt == DSM_DIA) && A->P.vdt == DSM_F64, DSM_E_UNSUPPORTED,
+                      "level matrices must be CSR or DIA with FP64 values");
+        }
+        for (int l = 0; l + 1 < nlevels; l++)
+            DSM_CHECK(f2c[l] || levels[l + 1]->nrows == 0, DSM_E_INVALID, "null f2c array");
+        DSM_HIP(hipSetDevice(ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        auto *mg = new dsm_mg_s();
+        mg->ctx = ctx;
+        mg->L.resize(nlevels);
+        try {
+            for (int l = 0; l < nlevels; l++)
+                build_level(mg, l, levels[l], colour[l], l + 1 < nlevels ? f2c[l] : nullptr,
+                            l + 1 < nlevels ? levels[l + 1]->nrows : 0, s);
+            const int64_t n = levels[0]->nrows;
+            const size_t nb = sizeof(double) * (size_t)std::max<int64_t>(n, 1);
+            mg->r = (double *)mg->alloc(nb);
+            mg->z = (double *)mg->alloc(nb);
+            mg->p = (double *)mg->alloc(nb);
+            mg->q = (double *)mg->alloc(nb);
+            mg->part_a = (double *)mg->alloc(sizeof(double) * pcg_partials(n));
+            mg->part_b = (double *)mg->alloc(sizeof(double) * pcg_partials(n));
+            mg->part_c = (double *)mg->alloc(sizeof(double) * pcg_partials(n));
+            mg->st = (CgState *)mg->alloc(sizeof(CgState));
+        } catch (...) {
+            (void)hipStreamSynchronize(s);
+            mg->release();
+            delete mg;
+            throw;
+        }
+        *out = mg;
+    });
+}
+
+DSM_API dsm_status dsm_mg_destroy(dsm_mg mg) {
+    return guard([&] {
+        if (!mg) return;
+        (void)hipSetDevice(mg->ctx->device);
+        (void)hipDeviceSynchronize();
+        mg->release();
+        delete mg;
+    });
+}
+
+DSM_API dsm_status dsm_mg_symgs(dsm_mg mg, int32_t level, const double *r, double *x, void *stream) {
+    return guard([&] {
+        DSM_CHECK(mg, DSM_E_INVALID, "null hierarchy");
+        DSM_CHECK(level >= 0 && level < (int)mg->L.size(), DSM_E_INVALID, "no such level");
+        auto &lv = mg->L[level];
+        DSM_CHECK((r && x) || lv.n == 0, DSM_E_INVALID, "null vector");
+        DSM_CHECK(r != x || lv.n == 0, DSM_E_INVALID, "r and x must not alias");
+        check_level_format(lv);
+        DSM_HIP(hipSetDevice(mg->ctx->device));
+        if (lv.n > 0) symgs(mg, level, r, x, (hipStream_t)stream, nullptr);
+    });
+}
+
+DSM_API dsm_status dsm_mg_apply(dsm_mg mg, const double *r, double *z, void *stream) {
+    return guard([&] {
+        DSM_CHECK(mg, DSM_E_INVALID, "null hierarchy");
+        const int64_t n = mg->L[0].n;
+        DSM_CHECK((r && z) || n == 0, DSM_E_INVALID, "null vector");
+        DSM_CHECK(r != z || n == 0, DSM_E_INVALID, "r and z must not alias");
+        for (auto &lv : mg->L) check_level_format(lv);
+        DSM_HIP(hipSetDevice(mg->ctx->device));
+        if (n > 0) vcycle(mg, 0, r, z, (hipStream_t)stream, nullptr);
+    });
+}
+
+DSM_API dsm_status dsm_pcg_mg_solve(dsm_mg mg, const double *b, double *x, const dsm_cg_opts *opts,
+                                    dsm_cg_result *result, void *stream) {
+    dsm_cg_result R{};
+    dsm_status st = guard([&] {
+        DSM_CHECK(mg && result, DSM_E_INVALID, "null argument");
+        const int64_t n = mg->L[0].n;
+        DSM_CHECK((b && x) || n == 0, DSM_E_INVALID, "null vector");
+        for (auto &lv : mg->L) check_level_format(lv);
+        DSM_HIP(hipSetDevice(mg->ctx->device));
+        dsm_cg_opts o;
+        dsm_cg_opts_default(&o);
+        if (opts) o = *opts;
+        DSM_CHECK(o.tol >= 0, DSM_E_INVALID, "negative tolerance");
+        hipStream_t s = (hipStream_t)stream;
+        if (n == 0) {
+            R.status = DSM_OK;
+            return;
+        }
+        const long long maxit = o.maxit > 0 ? o.maxit : std::min<long long>(10 * n, 20000);
+        const int every = o.check_every > 0 ? o.check_every : 4;
+        CgState h = run_pcg_mg(mg, b, x, o.tol, maxit, every, s);
+        R.iters = h.iters;
+        R.relres = h.relres;
+        R.status = h.done == 1 ? DSM_OK : h.done == 3 ? DSM_E_BREAKDOWN : DSM_E_NOT_CONVERGED;
+        // true residual ||b - A x|| / ||b|| with the level-0 matrix
+        auto &l0 = mg->L[0];
+        spmv(l0.A, l0.A->P, x, mg->q, DSM_F64, l0.A->variant, s, &l0.spws);
+        hipLaunchKernelGGL(k_pmg_norms, dim3(CGG), dim3(CGB), 0, s, n, b, mg->q, mg->part_b, mg->part_c);
+        DSM_HIP(hipGetLastError());
+        std::vector<double> pa(CGG), pb(CGG);
+        DSM_HIP(hipMemcpyAsync(pa.data(), mg->part_b, sizeof(double) * CGG, hipMemcpyDeviceToHost, s));
+        DSM_HIP(hipMemcpyAsync(pb.data(), mg->part_c, sizeof(double) * CGG, hipMemcpyDeviceToHost, s));
+        DSM_HIP(hipStreamSynchronize(s));
+        double rr = 0, bb = 0;
+        for (int i = 0; i < CGG; i++) {
+            rr += pa[i];
+            bb += pb[i];
+        }
+        R.relres_true = bb > 0 ? std::sqrt(rr) / std::sqrt(bb) : std::sqrt(rr);
+    });
+    if (result) *result = R;
+    if (st != DSM_OK) return st;
+    return R.status;
+}

@@ -56,57 +56,95 @@ static double time_spmv(dsm_matrix m, const Payload &P, int variant, const void 
 }
 
 // ---------------------------------------------------------------- model
-// Bytes a format would move for this structure (as spmv_bytes, from the
-// features alone) plus the extra traffic of x gathers that leave the cache
-// window around the diagonal (one 64-byte sector each, for formats that
-// gather through column indices).
+// Time of one SpMV predicted from the structure features: every format is
+// a sum of sweeps of four kernel classes (COO, CSR, DIA, ELL; HYB = ELL +
+// COO, HDC = DIA + CSR).  A sweep costs its traffic over the class's learned
+// bandwidth, at least its critical path, plus a launch overhead per kernel.
+// Traffic is the format's bytes (as spmv_bytes, from the features alone)
+// plus one 64-byte sector for each x gather that leaves the cache window
+// around the diagonal.  A CSR sweep's critical path is the longest row: one
+// workgroup takes it in passes of 1024 entries, each pass two dependent
+// memory round trips.
 constexpr i64 NEAR_WINDOW = 1 << 16;
 constexpr double FAR_BYTES = 64.0;
 constexpr double LAUNCH_US = 3.0;
+constexpr double ROW_PASS_US = 2.0;
+constexpr double LEARN_MIN_BYTES = 16e6;  // smaller sweeps are latency-bound
+enum { KC_COO = 0, KC_CSR = 1, KC_DIA = 2, KC_ELL = 3 };
+
+struct Sweep {
+    int kc = KC_CSR;
+    double traffic = 0, crit_us = 0;
+    int launches = 1;
+};
 
 struct Prediction {
     double bytes[6] = {0, 0, 0, 0, 0, 0};
-    double traffic[6] = {0, 0, 0, 0, 0, 0};
     int feasible[6] = {0, 0, 0, 0, 0, 0};
-    int launches[6] = {2, 1, 1, 1, 3, 2};
+    Sweep part[6][2];
+    int nparts[6] = {1, 1, 1, 1, 2, 2};
 };
 
-static Prediction predict_bytes(const dsm_matrix_s *m, const StructFeatures &F, int vdt, int vec,
-                                double max_pad_ratio) {
+static double csr_crit(i64 max_len) { return ROW_PASS_US * (double)std::max<i64>(1, (max_len + 1023) / 1024); }
+
+static Prediction predict(const dsm_matrix_s *m, const StructFeatures &F, int vdt, int vec, double max_pad_ratio) {
     Prediction P;
     const double v = (double)dtype_size(vdt), i = 4.0, X = (double)dtype_size(vec);
     const double N = (double)m->nrows, nnz = (double)F.nnz, xy = (double)m->ncols * X + N * X;
     const double far = (double)(F.nnz - F.near);
     const double ratio = max_pad_ratio > 0 ? max_pad_ratio : 16.0;
+    auto farof = [&](double part_nnz) { return nnz > 0 ? FAR_BYTES * far * part_nnz / nnz : 0.0; };
     P.bytes[DSM_COO] = nnz * (v + 2 * i) + xy;
     P.bytes[DSM_CSR] = nnz * (v + i) + (N + 1) * i + xy;
     P.bytes[DSM_DIA] = (double)F.ndiag * N * v + (double)F.ndiag * i + xy;
     P.bytes[DSM_ELL] = (double)F.max_len * N * (v + i) + xy;
-    P.bytes[DSM_HYB] = (double)F.hyb_width * N * (v + i) + (double)F.hyb_coo * (v + 2 * i) + xy;
+    const double coo_part = (double)F.hyb_coo, ell_part = nnz - coo_part;
+    P.bytes[DSM_HYB] = (double)F.hyb_width * N * (v + i) + coo_part * (v + 2 * i) + xy;
     const double rem = nnz - (double)F.hdc_dia_nnz;
     P.bytes[DSM_HDC] = (double)F.hdc_ndiag * N * v + (double)F.hdc_ndiag * i + rem * (v + i) + (N + 1) * i + xy;
-    for (int f = 0; f < 6; f++) {
-        P.feasible[f] = 1;
-        double fb = far;
-        if (f == DSM_DIA) fb = 0;
-        if (f == DSM_HDC) fb = nnz > 0 ? far * rem / nnz : 0;
-        P.traffic[f] = P.bytes[f] + FAR_BYTES * fb;
-    }
+
+    P.part[DSM_COO][0] = {KC_COO, P.bytes[DSM_COO] + farof(nnz), 0, 2};
+    P.part[DSM_CSR][0] = {KC_CSR, P.bytes[DSM_CSR] + farof(nnz), csr_crit(F.max_len), 1};
+    P.part[DSM_DIA][0] = {KC_DIA, P.bytes[DSM_DIA], 0, 1};
+    P.part[DSM_ELL][0] = {KC_ELL, P.bytes[DSM_ELL] + farof(nnz), 0, 1};
+    // the second part of HYB/HDC reads x again and updates the y rows it holds
+    P.part[DSM_HYB][0] = {KC_ELL, (double)F.hyb_width * N * (v + i) + xy + farof(ell_part), 0, 1};
+    P.part[DSM_HYB][1] = {KC_COO, coo_part * (v + 2 * i) + (double)m->ncols * X + 2 * std::min(coo_part, N) * X +
+                                      farof(coo_part), 0, 2};
+    P.part[DSM_HDC][0] = {KC_DIA, (double)F.hdc_ndiag * N * v + (double)F.hdc_ndiag * i + xy, 0, 1};
+    P.part[DSM_HDC][1] = {KC_CSR, rem * (v + i) + (N + 1) * i + (double)m->ncols * X + 2 * N * X + farof(rem),
+                          rem > 0 ? csr_crit(F.max_len) : 0.0, 1};
+    if (coo_part == 0) P.nparts[DSM_HYB] = 1;
+    for (int f = 0; f < 6; f++) P.feasible[f] = 1;
     if ((double)F.ndiag * N > ratio * std::max(nnz, 1.0)) P.feasible[DSM_DIA] = 0;
     if ((double)F.max_len * N > ratio * std::max(nnz, 1.0)) P.feasible[DSM_ELL] = 0;
     return P;
 }
 
-// Feeds one timed selection back into the context's bandwidth table.
+static double sweep_us(const Sweep &w, const double *bw) {
+    return std::max(w.traffic / (bw[w.kc] * 1e3), w.crit_us) + w.launches * LAUNCH_US;
+}
+
+static double predict_us(const Prediction &P, int f, const double *bw) {
+    double t = 0;
+    for (int k = 0; k < P.nparts[f]; k++) t += sweep_us(P.part[f][k], bw);
+    return t;
+}
+
+// Feeds one timed selection back into the context's bandwidth table: the
+// single-sweep formats give their class's bandwidth directly, when the sweep
+// was large enough to be bandwidth-bound.
 static void learn(dsm_ctx ctx, const Prediction &P, const dsm_select_report &R, const int *best_variant) {
     std::lock_guard<std::mutex> lk(ctx->cache_mu);
     for (int f = 0; f < 6; f++) {
         if (R.status[f] != DSM_OK || R.median_us[f] <= 0) continue;
-        const double t = R.median_us[f] - P.launches[f] * LAUNCH_US;
-        if (t <= 0 || P.traffic[f] <= 0) continue;
-        const double bw = P.traffic[f] / (t * 1e3);  // GB/s
-        ctx->model_bw[f] = 0.5 * ctx->model_bw[f] + 0.5 * bw;
         if (best_variant[f] >= 0) ctx->model_variant[f] = best_variant[f];
+        if (P.nparts[f] != 1 || f == DSM_HYB || f == DSM_HDC) continue;
+        const Sweep &w = P.part[f][0];
+        const double t = R.median_us[f] - w.launches * LAUNCH_US;
+        if (w.traffic < LEARN_MIN_BYTES || t <= 2.0 * w.crit_us) continue;
+        const double bw = w.traffic / (t * 1e3);  // GB/s
+        ctx->model_bw[w.kc] = 0.5 * ctx->model_bw[w.kc] + 0.5 * bw;
     }
 }
 
@@ -186,7 +224,7 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
         }
         tmp.release(ctx);
     }
-    const Prediction PR = predict_bytes(m, F, o.value_dtype, vec, o.max_pad_ratio);
+    const Prediction PR = predict(m, F, o.value_dtype, vec, o.max_pad_ratio);
 
     if (o.reps == 0 && o.target == 0) {
         // online choice: no profiling runs, the model picks
@@ -202,7 +240,7 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
                     continue;
                 }
                 R.status[f] = DSM_OK;
-                R.median_us[f] = PR.traffic[f] / (ctx->model_bw[f] * 1e3) + PR.launches[f] * LAUNCH_US;
+                R.median_us[f] = predict_us(PR, f, ctx->model_bw);
                 if (best < 0 || R.median_us[f] < bt) {
                     best = f;
                     bt = R.median_us[f];

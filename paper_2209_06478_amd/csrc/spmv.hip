@@ -152,10 +152,35 @@ struct alignas(2 * sizeof(V)) pair2 {
     V a, b;
 };
 
-template <class V, class X, bool ACC, bool XCD, int R, bool P2>
+// Square sweeps inside CG: the workgroup's partial of x . y (p . q with
+// x = p, y = q = A p) over its own rows, accumulated in FP64 and stored in
+// part[blockIdx.x]; workgroup 0 also counts the launch.  Every thread
+// reaches the barrier: the early exit on `stop` is uniform (the flag is
+// written only by other launches).
+template <class X, int R, int RW>
+__device__ __forceinline__ void dot_epilogue(const X (&s)[R][RW], const X *__restrict__ x, i64 i0, i64 nrows,
+                                             double *__restrict__ part, long long *count) {
+    __shared__ double lds[SB / WAVE];
+    double acc = 0;
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int w = 0; w < RW; w++) {
+            const i64 i = i0 + (i64)r * SB * RW + w;
+            if (i < nrows) acc += (double)x[i] * (double)s[r][w];
+        }
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = acc;
+        if (count && blockIdx.x == 0) *count += 1;
+    }
+}
+
+template <class V, class X, bool ACC, bool XCD, int R, bool P2, bool DOT = false>
 __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, const i32 *__restrict__ offs,
                                             const V *__restrict__ dval, i64 pitch, const X *__restrict__ x,
-                                            X *__restrict__ y, const int *__restrict__ stop) {
+                                            X *__restrict__ y, const int *__restrict__ stop,
+                                            double *__restrict__ part = nullptr, long long *count = nullptr) {
     if (stop && *stop) return;
     constexpr int RW = P2 ? 2 : 1;
     const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -192,12 +217,14 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
             const i64 i = i0 + (i64)r * SB * RW + w;
             if (i < nrows) store_y(y, i, s[r][w], ACC);
         }
+    if constexpr (DOT) dot_epilogue<X, R, RW>(s, x, i0, nrows, part, count);
 }
 
-template <class V, class X, bool ACC, bool XCD, int R, bool P2>
+template <class V, class X, bool ACC, bool XCD, int R, bool P2, bool DOT = false>
 __global__ void __launch_bounds__(SB) k_ell(i64 nrows, i64 K, i64 pitch, const i32 *__restrict__ ecol,
                                             const V *__restrict__ evl, const X *__restrict__ x, X *__restrict__ y,
-                                            const int *__restrict__ stop) {
+                                            const int *__restrict__ stop, double *__restrict__ part = nullptr,
+                                            long long *count = nullptr) {
     if (stop && *stop) return;
     constexpr int RW = P2 ? 2 : 1;
     const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -235,6 +262,7 @@ __global__ void __launch_bounds__(SB) k_ell(i64 nrows, i64 K, i64 pitch, const i
             const i64 i = i0 + (i64)r * SB * RW + w;
             if (i < nrows) store_y(y, i, s[r][w], ACC);
         }
+    if constexpr (DOT) dot_epilogue<X, R, RW>(s, x, i0, nrows, part, count);
 }
 
 // ---------------------------------------------------------------- COO
@@ -441,33 +469,42 @@ static void csr_launch(dsm_matrix m, const Payload &P, const X *x, X *y, int var
 #undef VEC
 }
 
-template <class V, class X, bool ACC, bool XCD, int R, bool P2>
-static void sweep_launch(dsm_matrix m, const Payload &P, const X *x, X *y, hipStream_t s, const int *stop) {
+// Launch geometry of a sweep variant (workgroups = partials of the dot form).
+static unsigned sweep_groups(i64 n, int variant) {
+    const int lr = (variant >> 1) & 3, R = lr == 0 ? 1 : (lr == 1 ? 2 : 4);
+    return grid_for(n, SB * R * (((variant >> 3) & 1) ? 2 : 1));
+}
+
+template <class V, class X, bool ACC, bool XCD, int R, bool P2, bool DOT>
+static void sweep_launch(dsm_matrix m, const Payload &P, const X *x, X *y, hipStream_t s, const int *stop,
+                         double *part, long long *count) {
     const i64 n = m->nrows;
     const unsigned g = grid_for(n, SB * R * (P2 ? 2 : 1));
     if (P.fmt == DSM_DIA || P.fmt == DSM_HDC)
-        hipLaunchKernelGGL((k_dia<V, X, ACC, XCD, R, P2>), dim3(g), dim3(SB), 0, s, n, m->ncols, P.ndiag, P.offs,
-                           (const V *)P.dval, P.pitch, x, y, stop);
+        hipLaunchKernelGGL((k_dia<V, X, ACC, XCD, R, P2, DOT>), dim3(g), dim3(SB), 0, s, n, m->ncols, P.ndiag,
+                           P.offs, (const V *)P.dval, P.pitch, x, y, stop, part, count);
     else
-        hipLaunchKernelGGL((k_ell<V, X, ACC, XCD, R, P2>), dim3(g), dim3(SB), 0, s, n, P.K, P.pitch, P.ecol,
-                           (const V *)P.evl, x, y, stop);
+        hipLaunchKernelGGL((k_ell<V, X, ACC, XCD, R, P2, DOT>), dim3(g), dim3(SB), 0, s, n, P.K, P.pitch, P.ecol,
+                           (const V *)P.evl, x, y, stop, part, count);
 }
 
-template <class V, class X, bool ACC, bool XCD, bool P2>
-static void sweep_r(dsm_matrix m, const Payload &P, const X *x, X *y, int lr, hipStream_t s, const int *stop) {
-    if (lr == 0) sweep_launch<V, X, ACC, XCD, 1, P2>(m, P, x, y, s, stop);
-    else if (lr == 1) sweep_launch<V, X, ACC, XCD, 2, P2>(m, P, x, y, s, stop);
-    else sweep_launch<V, X, ACC, XCD, 4, P2>(m, P, x, y, s, stop);
+template <class V, class X, bool ACC, bool XCD, bool P2, bool DOT>
+static void sweep_r(dsm_matrix m, const Payload &P, const X *x, X *y, int lr, hipStream_t s, const int *stop,
+                    double *part, long long *count) {
+    if (lr == 0) sweep_launch<V, X, ACC, XCD, 1, P2, DOT>(m, P, x, y, s, stop, part, count);
+    else if (lr == 1) sweep_launch<V, X, ACC, XCD, 2, P2, DOT>(m, P, x, y, s, stop, part, count);
+    else sweep_launch<V, X, ACC, XCD, 4, P2, DOT>(m, P, x, y, s, stop, part, count);
 }
 
-template <class V, class X, bool ACC>
-static void sweep(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s, const int *stop) {
+template <class V, class X, bool ACC, bool DOT = false>
+static void sweep(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s, const int *stop,
+                  double *part = nullptr, long long *count = nullptr) {
     const bool xcd = !(variant & 1), p2 = (variant >> 3) & 1;
     const int lr = (variant >> 1) & 3;
-    if (xcd && p2) sweep_r<V, X, ACC, true, true>(m, P, x, y, lr, s, stop);
-    else if (xcd) sweep_r<V, X, ACC, true, false>(m, P, x, y, lr, s, stop);
-    else if (p2) sweep_r<V, X, ACC, false, true>(m, P, x, y, lr, s, stop);
-    else sweep_r<V, X, ACC, false, false>(m, P, x, y, lr, s, stop);
+    if (xcd && p2) sweep_r<V, X, ACC, true, true, DOT>(m, P, x, y, lr, s, stop, part, count);
+    else if (xcd) sweep_r<V, X, ACC, true, false, DOT>(m, P, x, y, lr, s, stop, part, count);
+    else if (p2) sweep_r<V, X, ACC, false, true, DOT>(m, P, x, y, lr, s, stop, part, count);
+    else sweep_r<V, X, ACC, false, false, DOT>(m, P, x, y, lr, s, stop, part, count);
 }
 
 template <class V, class X, bool ACC>
@@ -518,6 +555,26 @@ void spmv(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int v
         default: acc ? spmv_typed<bf16, float, true>(m, P, xx, yy, variant, s, scratch, stop) : spmv_typed<bf16, float, false>(m, P, xx, yy, variant, s, scratch, stop); break;
         }
     }
+}
+
+template <class X>
+static int spmv_dot_typed(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s,
+                          double *part, long long *count, const int *stop) {
+    switch (P.vdt) {
+    case DSM_F64: sweep<double, X, false, true>(m, P, x, y, variant, s, stop, part, count); break;
+    case DSM_F32: sweep<float, X, false, true>(m, P, x, y, variant, s, stop, part, count); break;
+    default: sweep<bf16, X, false, true>(m, P, x, y, variant, s, stop, part, count); break;
+    }
+    DSM_HIP(hipGetLastError());
+    return (int)sweep_groups(m->nrows, variant);
+}
+
+int spmv_dot(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant, hipStream_t s,
+             double *part, long long *count, const int *stop) {
+    if (!(P.fmt == DSM_DIA || P.fmt == DSM_ELL) || m->nrows != m->ncols || m->nrows == 0) return 0;
+    if (vdt == DSM_F64)
+        return spmv_dot_typed<double>(m, P, (const double *)x, (double *)y, variant, s, part, count, stop);
+    return spmv_dot_typed<float>(m, P, (const float *)x, (float *)y, variant, s, part, count, stop);
 }
 
 double spmv_bytes(const dsm_matrix_s *m, const Payload &P, int vec_dtype) {

@@ -128,10 +128,11 @@ def test_cg_graph_replay_matches_eager():
 
 
 @pytest.mark.parametrize("fmt", ["dia", "ell"])
-@pytest.mark.parametrize("variant", [0, 4, 9])
+@pytest.mark.parametrize("variant", [0, 4, 9, 10])
 def test_cg_fused_iteration_matches_oracle(fmt, variant):
-    """DIA/ELL solves use the two-kernel fused iteration; it passes the same
-    oracle checks as the four-kernel loop, and the two agree within +-1 iteration."""
+    """DIA/ELL solves run the three-kernel loop whose SpMV also writes the
+    p.q partials, or (DSM_CG_FUSED=1) the two-kernel loop that forms p on
+    the fly; both pass the oracle checks and agree within +-1 iteration."""
     import os
     torch, dev = torch_dev()
     p = problem("hpcg16")
@@ -140,10 +141,10 @@ def test_cg_fused_iteration_matches_oracle(fmt, variant):
     A.convert(fmt)
     A.variant = variant
     b = torch.from_numpy(p.b).to(dev)
-    xf, rf = A.cg(b)
-    os.environ["DSM_CG_FUSED"] = "0"
+    xu, ru = A.cg(b)
+    os.environ["DSM_CG_FUSED"] = "1"
     try:
-        xu, ru = A.cg(b)
+        xf, rf = A.cg(b)
     finally:
         os.environ.pop("DSM_CG_FUSED", None)
     for x, r in ((xf, rf), (xu, ru)):
@@ -154,17 +155,23 @@ def test_cg_fused_iteration_matches_oracle(fmt, variant):
     A.close()
 
 
-def test_cg_fused_maxit_and_breakdown():
+@pytest.mark.parametrize("fused", ["0", "1"])
+def test_cg_fused_maxit_and_breakdown(fused):
+    import os
     torch, dev = torch_dev()
     p = problem("hpcg16")
     A = make_matrix(p)
     A.convert("dia")
-    x, res = A.cg(torch.from_numpy(p.b).to(dev), maxit=5)
-    assert res["status"] == "not_converged" and res["iters"] == 5
-    x, res = A.cg(torch.from_numpy(p.b).to(dev), maxit=5, check_every=3)
-    assert res["status"] == "not_converged" and res["iters"] == 5
-    bb = p.b.copy()
-    bb[100] = np.inf
-    x, res = A.cg(torch.from_numpy(bb).to(dev))
-    assert res["status"] == "breakdown"
+    os.environ["DSM_CG_FUSED"] = fused
+    try:
+        x, res = A.cg(torch.from_numpy(p.b).to(dev), maxit=5)
+        assert res["status"] == "not_converged" and res["iters"] == 5
+        x, res = A.cg(torch.from_numpy(p.b).to(dev), maxit=5, check_every=3)
+        assert res["status"] == "not_converged" and res["iters"] == 5
+        bb = p.b.copy()
+        bb[100] = np.inf
+        x, res = A.cg(torch.from_numpy(bb).to(dev))
+        assert res["status"] == "breakdown"
+    finally:
+        os.environ.pop("DSM_CG_FUSED", None)
     A.close()
