@@ -46,6 +46,28 @@ def event_times_us(torch, fn, steps):
     return [a.elapsed_time(b) * 1000.0 for a, b in ev]
 
 
+def cg_leg(A, p, torch, dev, solves):
+    """CG to 1e-10 on the matrix in its current format: solves/s, p50/p99
+    latency and time per iteration (the first solve, which captures the
+    iteration graph, is not counted)."""
+    import numpy as np
+    b = torch.from_numpy(p.b).to(dev)
+    lat = []
+    res = None
+    for i in range(solves + 1):
+        xs = torch.zeros(p.nrows, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        xs, res = A.cg(b, x=xs, tol=1e-10)
+        lat.append((time.perf_counter() - t1) * 1e3)
+    lat = np.array(lat[1:])
+    return {"format": A.info()["format_name"], "variant": A.variant, "tol": 1e-10, "iters": res["iters"],
+            "status": res["status"], "relres_true": res["relres_true"],
+            "solves_per_s": round(1e3 / float(lat.mean()), 3),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "ms_per_iter": round(float(lat.mean()) / max(res["iters"], 1), 4)}
+
+
 def stream_ceilings(dsm, torch, dev, mib=2048, reps=10):
     """The library's own streaming kernels over a 2 GiB buffer: read-reduce
     (a matrix sweep's pattern), copy and write; GB/s from the median launch."""
@@ -109,7 +131,9 @@ def ir_bench(dsm, ctx, torch, dev, n=128):
         for label, fmt, vdt, mode in (("f64_csr", "csr", "f64", "f64"), ("f64_dia", "dia", "f64", "f64"),
                                       ("ir_f32_dia", "dia", "f32", "ir"), ("ir_bf16_dia", "dia", "bf16", "ir")):
             A = dsm.Matrix.from_csr(ctx, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
-            A.convert(fmt, value_dtype=vdt)
+            # the format is fixed; the kernel variant is tuned for the vector
+            # type the loop's SpMV runs in (FP32 inside IR)
+            A.select(mask=[fmt], value_dtype=vdt, vec_dtype="f32" if mode == "ir" else "f64", use_cache=False)
             ts, res, x = [], None, None
             for rep in range(3):
                 x0 = torch.zeros(p.nrows, dtype=torch.float64, device=dev)
@@ -117,7 +141,8 @@ def ir_bench(dsm, ctx, torch, dev, n=128):
                 t0 = time.perf_counter()
                 x, res = A.cg(b, x=x0, tol=1e-10, mode=mode)
                 ts.append(time.perf_counter() - t0)
-            row[label] = {"ms": round(min(ts) * 1e3, 3), "iters": res["iters"], "outer": res["outer_iters"],
+            row[label] = {"ms": round(min(ts) * 1e3, 3), "variant": A.variant, "iters": res["iters"],
+                          "outer": res["outer_iters"],
                           "relres_true": res["relres_true"], "status": res["status"],
                           "err_vs_ones": float(torch.linalg.norm(x - 1.0) / np.sqrt(p.nrows))}
             A.close()
@@ -364,6 +389,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--format", default=None, help="force a format instead of selecting")
     ap.add_argument("--variant", type=int, default=None, help="kernel variant with --format")
+    ap.add_argument("--leg", default=None, choices=["cg", "pcg_mg", "ir_cg", "split", "irregular", "serving"],
+                    help="run only this leg (after the matrix set-up) and print its JSON; for profiling")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, run a device copy of this many MiB `steps` times "
                          "(calibration kernel of known size for the HBM byte counters)")
@@ -394,6 +421,20 @@ def main():
 
     def spmv():
         A.spmv(x, out=y)
+
+    if args.leg:
+        legs = {"cg": lambda: cg_leg(A, p, torch, dev, args.cg_solves),
+                "pcg_mg": lambda: mg_bench(dsm, ctx, torch, dev, n=args.n),
+                "ir_cg": lambda: ir_bench(dsm, ctx, torch, dev),
+                "split": lambda: split_bench(dsm, ctx, torch, dev, n=args.n),
+                "irregular": lambda: irregular_bench(dsm, ctx, torch, dev),
+                "serving": lambda: serving_bench(dsm, ctx, torch, dev, nreq=args.serve_requests)}
+        if args.leg == "cg":
+            A.select(use_cache=False)
+        print(json.dumps({"leg": args.leg, "workload": f"hpcg27_{args.n}", "result": legs[args.leg]()}), flush=True)
+        A.close()
+        ctx.close()
+        return
 
     # fixed CSR (default kernel) for the comparison
     log("[bench] fixed CSR")
@@ -445,19 +486,22 @@ def main():
     value = sel_bytes / (ms_per_step * 1e-3) / 1e9
     achieved = sel_bytes / (avg_us * 1e-6) / 1e9
 
-    # warm (back to back, what CG sees) vs cold (a 1 GiB write evicts L2
-    # and the 256 MB Infinity Cache before each launch) per-launch times
+    # warm (back to back, what CG sees) vs cold (reading a 1 GiB buffer
+    # evicts L2 and the 256 MB Infinity Cache with clean lines before each
+    # launch, so no write-back of the flush lands in the timed launch)
     ceil = None
     cache = None
     if not args.only_spmv:
         log("[bench] streaming ceilings and cold-cache SpMV")
         ceil = stream_ceilings(dsm, torch, dev)
-        flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        flush = torch.zeros(1 << 27, dtype=torch.float64, device=dev)
+        fpart = torch.empty(dsm.PROBE_PARTIALS, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
         cold = []
         for _ in range(args.steps // 4 + 5):
-            dsm.stream_probe("write", flush)
+            dsm.stream_probe("read", fpart, flush)
             cold += event_times_us(torch, spmv, 1)
-        del flush
+        del flush, fpart
         cold = np.array(cold[5:])
         warm = np.array(ev_us)
         cache = {m: {"median_us": round(float(np.median(t)), 3), "p90_us": round(float(np.percentile(t, 90)), 3),
@@ -482,20 +526,7 @@ def main():
     cg = None
     if not args.only_spmv and args.cg_solves > 0:
         log("[bench] CG solves")
-        b = torch.from_numpy(p.b).to(dev)
-        lat = []
-        res = None
-        for i in range(args.cg_solves + 1):
-            xs = torch.zeros(N, dtype=torch.float64, device=dev)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            xs, res = A.cg(b, x=xs, tol=1e-10)
-            lat.append((time.perf_counter() - t1) * 1e3)
-        lat = np.array(lat[1:])
-        cg = {"format": fmt, "tol": 1e-10, "iters": res["iters"], "status": res["status"],
-              "relres_true": res["relres_true"], "solves_per_s": round(1e3 / float(lat.mean()), 3),
-              "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-              "ms_per_iter": round(float(lat.mean()) / max(res["iters"], 1), 4)}
+        cg = cg_leg(A, p, torch, dev, args.cg_solves)
 
     irr = None if (args.only_spmv or args.no_irregular) else irregular_bench(dsm, ctx, torch, dev)
     ir = None if (args.only_spmv or args.no_ir) else ir_bench(dsm, ctx, torch, dev)

@@ -712,8 +712,12 @@ void cg_solve_ws(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o,
         hipLaunchKernelGGL(k_scale_down, dim3(CGG), dim3(CGB), 0, s, n, B.r, B.norms, B.r32, B.d32);
         DSM_HIP(hipGetLastError());
         // the scaled residual r32 is the inner right-hand side, d32 the inner iterate
+        // the inner solve need not reduce the residual further than the
+        // outer tolerance asks (with a factor 2 of margin): the last outer
+        // step usually needs far less than inner_tol
+        const double tau = std::min(0.5, std::max(inner_tol, 0.5 * o.tol / relres));
         CgState h = run_cg<float>(m, B.r32, B.d32, B.ri32, B.p32, B.q32, B.p32b, B.part_a, B.part_b, B.st2, DSM_F32,
-                                  inner_tol, std::max<long long>(1, maxit - inner_total), every, s, spws,
+                                  tau, std::max<long long>(1, maxit - inner_total), every, s, spws,
                                   cgws, use_graph);
         inner_total += h.iters;
         if (h.done == 3 && h.iters <= 1) {

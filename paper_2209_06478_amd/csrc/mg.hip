@@ -31,6 +31,7 @@ namespace dsm {
 
 constexpr int MB = 256;      // threads per workgroup
 constexpr int GSW = 8;       // CSR lanes per row in the smoother
+constexpr int GSR = 1;       // DIA rows per thread in the smoother
 constexpr int MG_MAX_LEVELS = 8;
 
 }  // namespace dsm
@@ -46,6 +47,7 @@ struct dsm_mg_s {
         double *diag = nullptr;
         int32_t *f2c = nullptr;         // next level's rows -> rows of this level
         double *dperm = nullptr;        // DIA: diagonals in colour order (same pitch)
+        int64_t *cstart_d = nullptr;    // cstart on the device (one-workgroup sweep)
         double *r = nullptr, *x = nullptr, *ax = nullptr;
         dsm::Workspace spws;
     };
@@ -86,6 +88,7 @@ __global__ void __launch_bounds__(MB) k_symgs_csr(i64 cnt, const i32 *__restrict
                                                   const double *__restrict__ diag, const double *__restrict__ r,
                                                   double *__restrict__ x, const int *stop) {
     if (stopped(stop)) return;  // the flag is written only by other launches
+    constexpr int U = 4;        // entries a lane loads before its x gathers
     const i64 g = ((i64)blockIdx.x * MB + threadIdx.x) / W;
     const int lane = threadIdx.x % W;
     double s = 0;
@@ -93,9 +96,18 @@ __global__ void __launch_bounds__(MB) k_symgs_csr(i64 cnt, const i32 *__restrict
     if (g < cnt) {
         i = rows[g];
         const i64 e1 = rp[i + 1];
-        for (i64 k = rp[i] + lane; k < e1; k += W) {
-            const i32 c = col[k];
-            if (c != i) s += val[k] * x[c];
+        for (i64 base = rp[i] + lane; base < e1; base += (i64)U * W) {
+            i32 c[U];
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const i64 k = base + (i64)u * W;
+                c[u] = k < e1 ? col[k] : (i32)i;
+                v[u] = k < e1 ? val[k] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                if (c[u] != i) s += v[u] * x[c[u]];
         }
     }
     s = group_sum<W>(s);
@@ -106,23 +118,38 @@ __global__ void __launch_bounds__(MB) k_symgs_csr(i64 cnt, const i32 *__restrict
 // diagonal k holds A(rows[t], rows[t] + off_k), so a colour's rows are a
 // contiguous, coalesced range of every diagonal (in the natural layout they
 // would be every other slot, wasting half of each line fetched).
+template <int R>
 __global__ void __launch_bounds__(MB) k_symgs_dia(i64 t0, i64 cnt, const i32 *__restrict__ rows, i64 n, i64 ndiag,
                                                   const i32 *__restrict__ offs, const double *__restrict__ dperm,
                                                   i64 pitch, const double *__restrict__ diag,
                                                   const double *__restrict__ r, double *__restrict__ x,
                                                   const int *stop) {
     if (stopped(stop)) return;
-    const i64 g = (i64)blockIdx.x * MB + threadIdx.x;
-    if (g >= cnt) return;
-    const i64 t = t0 + g;
-    const i64 i = rows[t];
-    double s = 0;
+    // R rows per thread, each with its own sum, and the diagonal loop
+    // unrolled: several independent loads in flight per thread
+    const i64 g0 = (i64)blockIdx.x * MB * R + threadIdx.x;
+    i64 i[R];
+    double s[R];
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+        const i64 g = g0 + (i64)q * MB;
+        i[q] = g < cnt ? rows[t0 + g] : -1;
+        s[q] = 0;
+    }
+#pragma unroll 9
     for (i64 k = 0; k < ndiag; k++) {
         const i64 off = offs[k];
-        const i64 j = i + off;
-        if (off != 0 && j >= 0 && j < n) s += dperm[k * pitch + t] * x[j];
+        if (off == 0) continue;
+        const double *dk = dperm + k * pitch + t0;
+#pragma unroll
+        for (int q = 0; q < R; q++) {
+            const i64 j = i[q] + off;
+            if (i[q] >= 0 && j >= 0 && j < n) s[q] += dk[g0 + (i64)q * MB] * x[j];
+        }
     }
-    x[i] = (r[i] - s) / diag[i];
+#pragma unroll
+    for (int q = 0; q < R; q++)
+        if (i[q] >= 0) x[i[q]] = (r[i[q]] - s[q]) / diag[i[q]];
 }
 
 __global__ void k_dia_colour_order(i64 n, i64 ndiag, const double *__restrict__ dval, i64 pitch,
@@ -131,6 +158,73 @@ __global__ void k_dia_colour_order(i64 n, i64 ndiag, const double *__restrict__ 
     if (t >= n) return;
     const i64 i = rows[t];
     for (i64 k = 0; k < ndiag; k++) dperm[k * pitch + t] = dval[k * pitch + i];
+}
+
+// Small levels: the whole sweep (every colour, forward then backward) in
+// one workgroup, colours separated by barriers, instead of one launch per
+// colour (a launch costs more than a small colour's work).
+constexpr int SBT = 1024;                 // threads of the one-workgroup sweep
+constexpr i64 BLOCK_LEVEL_ROWS = 8192;    // levels up to this size use it
+
+__device__ __forceinline__ int sweep_colour(int step, int nc) { return step < nc ? step : 2 * nc - 2 - step; }
+
+__global__ void __launch_bounds__(SBT) k_symgs_dia_block(int nc, const i64 *__restrict__ cstart,
+                                                         const i32 *__restrict__ rows, i64 n, i64 ndiag,
+                                                         const i32 *__restrict__ offs,
+                                                         const double *__restrict__ dperm, i64 pitch,
+                                                         const double *__restrict__ diag,
+                                                         const double *__restrict__ r, double *x, const int *stop) {
+    if (stopped(stop)) return;
+    for (int step = 0; step < 2 * nc - 1; step++) {
+        const int c = sweep_colour(step, nc);
+        const i64 t1 = cstart[c + 1];
+        for (i64 t = cstart[c] + threadIdx.x; t < t1; t += SBT) {
+            const i64 i = rows[t];
+            double s = 0;
+#pragma unroll 9
+            for (i64 k = 0; k < ndiag; k++) {
+                const i64 off = offs[k];
+                const i64 j = i + off;
+                if (off != 0 && j >= 0 && j < n) s += dperm[k * pitch + t] * x[j];
+            }
+            x[i] = (r[i] - s) / diag[i];
+        }
+        __syncthreads();  // the next colour reads this colour's updates
+    }
+}
+
+template <int W>
+__global__ void __launch_bounds__(SBT) k_symgs_csr_block(int nc, const i64 *__restrict__ cstart,
+                                                         const i32 *__restrict__ rows, const i32 *__restrict__ rp,
+                                                         const i32 *__restrict__ col,
+                                                         const double *__restrict__ val,
+                                                         const double *__restrict__ diag,
+                                                         const double *__restrict__ r, double *x, const int *stop) {
+    if (stopped(stop)) return;
+    const int lane = threadIdx.x % W, grp = threadIdx.x / W;
+    constexpr int G = SBT / W;
+    for (int step = 0; step < 2 * nc - 1; step++) {
+        const int c = sweep_colour(step, nc);
+        const i64 t0 = cstart[c], t1 = cstart[c + 1];
+        // every lane of a row group runs the same number of rounds (the
+        // shuffle reduction needs all W lanes)
+        for (i64 tb = t0; tb < t1; tb += G) {
+            const i64 t = tb + grp;
+            double s = 0;
+            i64 i = 0;
+            if (t < t1) {
+                i = rows[t];
+                const i64 e1 = rp[i + 1];
+                for (i64 k = rp[i] + lane; k < e1; k += W) {
+                    const i32 cc = col[k];
+                    if (cc != i) s += val[k] * x[cc];
+                }
+            }
+            s = group_sum<W>(s);
+            if (t < t1 && lane == 0) x[i] = (r[i] - s) / diag[i];
+        }
+        __syncthreads();
+    }
 }
 
 __global__ void k_mg_zero(i64 n, double *x, const int *stop) {
@@ -335,6 +429,17 @@ static void symgs(dsm_mg_s *mg, int l, const double *r, double *x, hipStream_t s
     auto &lv = mg->L[l];
     const Payload &P = lv.A->P;
     const int nc = (int)lv.cstart.size() - 1;
+    if (nc == 0) return;
+    if (lv.n <= BLOCK_LEVEL_ROWS) {
+        if (lv.fmt == DSM_CSR)
+            hipLaunchKernelGGL(k_symgs_csr_block<GSW>, dim3(1), dim3(SBT), 0, s, nc, lv.cstart_d, lv.rows, P.rp,
+                               P.col, (const double *)P.val, lv.diag, r, x, stop);
+        else
+            hipLaunchKernelGGL(k_symgs_dia_block, dim3(1), dim3(SBT), 0, s, nc, lv.cstart_d, lv.rows, lv.n, P.ndiag,
+                               P.offs, lv.dperm, P.pitch, lv.diag, r, x, stop);
+        DSM_HIP(hipGetLastError());
+        return;
+    }
     auto colour = [&](int c) {
         const i64 c0 = lv.cstart[c], cnt = lv.cstart[c + 1] - c0;
         if (cnt == 0) return;
@@ -342,8 +447,8 @@ static void symgs(dsm_mg_s *mg, int l, const double *r, double *x, hipStream_t s
             hipLaunchKernelGGL(k_symgs_csr<GSW>, dim3(grid_for(cnt * GSW, MB)), dim3(MB), 0, s, cnt, lv.rows + c0,
                                P.rp, P.col, (const double *)P.val, lv.diag, r, x, stop);
         else
-            hipLaunchKernelGGL(k_symgs_dia, dim3(grid_for(cnt, MB)), dim3(MB), 0, s, c0, cnt, lv.rows, lv.n,
-                               P.ndiag, P.offs, lv.dperm, P.pitch, lv.diag, r, x, stop);
+            hipLaunchKernelGGL(k_symgs_dia<GSR>, dim3(grid_for(cnt, MB * GSR)), dim3(MB), 0, s, c0, cnt, lv.rows,
+                               lv.n, P.ndiag, P.offs, lv.dperm, P.pitch, lv.diag, r, x, stop);
     };
     for (int c = 0; c < nc; c++) colour(c);
     for (int c = nc - 2; c >= 0; c--) colour(c);
@@ -389,6 +494,9 @@ static void build_level(dsm_mg_s *mg, int l, dsm_matrix A, const int32_t *colour
         for (i64 i = 0; i < n; i++) rows[pos[colour_h[i]]++] = (int32_t)i;
     }
     lv.rows = (int32_t *)mg->alloc(sizeof(int32_t) * rows.size());
+    lv.cstart_d = (int64_t *)mg->alloc(sizeof(int64_t) * lv.cstart.size());
+    DSM_HIP(hipMemcpyAsync(lv.cstart_d, lv.cstart.data(), sizeof(int64_t) * lv.cstart.size(), hipMemcpyHostToDevice,
+                           s));
     lv.diag = (double *)mg->alloc(sizeof(double) * (size_t)std::max<i64>(n, 1));
     int32_t *col_d = (int32_t *)dev_alloc(mg->ctx, sizeof(int32_t) * (size_t)std::max<i64>(n, 1));
     int *bad = (int *)dev_alloc(mg->ctx, 2 * sizeof(int));

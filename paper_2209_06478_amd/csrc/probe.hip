@@ -1,52 +1,64 @@
 // Streaming probes: the practical HBM ceiling that SpMV kernels are judged
 // against.  A read-reduce (the access pattern of a matrix sweep: read only,
 // a few bytes written), a copy and a write-only fill, each moving 16 B per
-// lane per load/store with four independent accesses in flight per lane.
+// lane per access.
 #include "core.hpp"
 
 namespace dsm {
 
 constexpr int PB = 256;
-constexpr int PU = 4;
+constexpr int PU = 16;
 
 struct alignas(16) d2 {
     double a, b;
 };
 
+// Each workgroup streams one contiguous chunk (1/gridDim of the buffer),
+// PU loads of 16 B per lane in flight; contiguous chunks keep DRAM pages
+// open (a grid-stride walk measured about 10% slower on MI355X).
+__device__ __forceinline__ void chunk_of(i64 n, i64 &b0, i64 &b1) {
+    const i64 per = (n + gridDim.x - 1) / gridDim.x;
+    b0 = min((i64)blockIdx.x * per, n);
+    b1 = min(b0 + per, n);
+}
+
 __global__ void __launch_bounds__(PB) k_probe_read(const d2 *__restrict__ src, i64 n, double *__restrict__ part) {
-    const i64 stride = (i64)gridDim.x * PB;
-    i64 i = (i64)blockIdx.x * PB + threadIdx.x;
+    i64 b0, b1;
+    chunk_of(n, b0, b1);
     double s = 0.0;
-    for (; i + (PU - 1) * stride < n; i += PU * stride) {
+    i64 i = b0 + threadIdx.x;
+    for (; i + (PU - 1) * PB < b1; i += PU * PB) {
         d2 v[PU];
 #pragma unroll
-        for (int u = 0; u < PU; u++) v[u] = src[i + u * stride];
+        for (int u = 0; u < PU; u++) v[u] = src[i + u * PB];
 #pragma unroll
         for (int u = 0; u < PU; u++) s += v[u].a + v[u].b;
     }
-    for (; i < n; i += stride) s += src[i].a + src[i].b;
+    for (; i < b1; i += PB) s += src[i].a + src[i].b;
     __shared__ double lds[PB / WAVE];
     s = block_sum(s, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 __global__ void __launch_bounds__(PB) k_probe_copy(const d2 *__restrict__ src, d2 *__restrict__ dst, i64 n) {
-    const i64 stride = (i64)gridDim.x * PB;
-    i64 i = (i64)blockIdx.x * PB + threadIdx.x;
-    for (; i + (PU - 1) * stride < n; i += PU * stride) {
+    i64 b0, b1;
+    chunk_of(n, b0, b1);
+    i64 i = b0 + threadIdx.x;
+    for (; i + (PU - 1) * PB < b1; i += PU * PB) {
         d2 v[PU];
 #pragma unroll
-        for (int u = 0; u < PU; u++) v[u] = src[i + u * stride];
+        for (int u = 0; u < PU; u++) v[u] = src[i + u * PB];
 #pragma unroll
-        for (int u = 0; u < PU; u++) dst[i + u * stride] = v[u];
+        for (int u = 0; u < PU; u++) dst[i + u * PB] = v[u];
     }
-    for (; i < n; i += stride) dst[i] = src[i];
+    for (; i < b1; i += PB) dst[i] = src[i];
 }
 
 __global__ void __launch_bounds__(PB) k_probe_write(d2 *__restrict__ dst, i64 n) {
-    const i64 stride = (i64)gridDim.x * PB;
+    i64 b0, b1;
+    chunk_of(n, b0, b1);
     const d2 z{0.0, 0.0};
-    for (i64 i = (i64)blockIdx.x * PB + threadIdx.x; i < n; i += stride) dst[i] = z;
+    for (i64 i = b0 + threadIdx.x; i < b1; i += PB) dst[i] = z;
 }
 
 }  // namespace dsm
