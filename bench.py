@@ -46,6 +46,19 @@ def event_times_us(torch, fn, steps):
     return [a.elapsed_time(b) * 1000.0 for a, b in ev]
 
 
+def alg_bytes(info, N, nnz, v=8, X=8):
+    """Algorithmic bytes of one SpMV in the active format (FP64 values and
+    vectors by default): the stored arrays once, x read once, y written once."""
+    return {
+        "csr": nnz * (v + 4) + (N + 1) * 4 + 2 * X * N,
+        "coo": nnz * (v + 8) + 2 * X * N,
+        "dia": info["ndiag"] * N * v + info["ndiag"] * 4 + 2 * X * N,
+        "ell": info["ell_width"] * N * (v + 4) + 2 * X * N,
+        "hyb": info["ell_width"] * N * (v + 4) + info["coo_nnz"] * (v + 8) + 2 * X * N,
+        "hdc": info["ndiag"] * N * v + info["ndiag"] * 4 + info["csr_nnz"] * (v + 4) + (N + 1) * 4 + 2 * X * N,
+    }[info["format_name"]]
+
+
 def cg_leg(A, p, torch, dev, solves):
     """CG to 1e-10 on the matrix in its current format: solves/s, p50/p99
     latency and time per iteration (the first solve, which captures the
@@ -61,7 +74,16 @@ def cg_leg(A, p, torch, dev, solves):
         xs, res = A.cg(b, x=xs, tol=1e-10)
         lat.append((time.perf_counter() - t1) * 1e3)
     lat = np.array(lat[1:])
-    return {"format": A.info()["format_name"], "variant": A.variant, "tol": 1e-10, "iters": res["iters"],
+    info = A.info()
+    N = p.nrows
+    # per iteration: one SpMV (the format's bytes) plus the vector kernels:
+    # update x, r (read x, p, r, q; write x, r) and p (read r, p; write p)
+    # = 80 N bytes, and 16 N more for a separate p.q kernel (not DIA/ELL)
+    vec = 80 * N + (0 if info["format_name"] in ("dia", "ell") else 16 * N)
+    it_bytes = alg_bytes(info, N, p.nnz) + vec
+    return {"format": info["format_name"], "variant": A.variant, "tol": 1e-10, "iters": res["iters"],
+            "bytes_per_iter": int(it_bytes),
+            "effective_gbps": round(it_bytes / (float(lat.mean()) * 1e-3 / max(res["iters"], 1)) / 1e9, 1),
             "status": res["status"], "relres_true": res["relres_true"],
             "solves_per_s": round(1e3 / float(lat.mean()), 3),
             "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
@@ -111,10 +133,21 @@ def cpu_baseline(p, budget_s=12.0):
     while time.perf_counter() - t1 < 3.0:
         oracle.cg(q.row_ptr, q.col, q.val, q.b, tol=1e-10)
         ncg += 1
+    cg_rate = ncg / (time.perf_counter() - t1)
+    # one thread, a few SpMVs
+    oracle.set_threads(1)
+    t2, reps1 = time.perf_counter(), 0
+    while time.perf_counter() - t2 < 3.0 and reps1 < 20:
+        oracle.spmv_csr(p.row_ptr, p.col, p.val, x)
+        reps1 += 1
+    dt1 = (time.perf_counter() - t2) / reps1
+    oracle.set_threads(cores)
     return {"value": round(bytes_ / dt / 1e9, 2), "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "single_thread_gbps": round(bytes_ / dt1 / 1e9, 2), "cg_solves_per_s_hpcg16_single_thread":
+            round(cg_rate, 1),
             "sample": f"{reps} oracle CSR SpMVs (FP64, OpenMP rows) on the full {p.name} matrix, "
-                      f"{dt * 1e3:.1f} ms each; oracle CG on hpcg27_16: "
-                      f"{ncg / (time.perf_counter() - t1):.1f} solves/s single-threaded"}
+                      f"{dt * 1e3:.1f} ms each ({reps1} more on one thread, {dt1 * 1e3:.1f} ms each); "
+                      f"oracle CG on hpcg27_16 single-threaded for 3 s"}
 
 
 def ir_bench(dsm, ctx, torch, dev, n=128):
@@ -458,17 +491,8 @@ def main():
         log(f"[bench] chose {sel['chosen']} variant {sel['chosen_variant']}")
     info = A.info()
     fmt = info["format_name"]
-    vdt_b = 8
     N, nnz = p.nrows, p.nnz
-    bytes_by_fmt = {
-        "csr": nnz * (vdt_b + 4) + (N + 1) * 4 + 16 * N,
-        "coo": nnz * (vdt_b + 8) + 16 * N,
-        "dia": info["ndiag"] * N * vdt_b + info["ndiag"] * 4 + 16 * N,
-        "ell": info["ell_width"] * N * (vdt_b + 4) + 16 * N,
-        "hyb": info["ell_width"] * N * (vdt_b + 4) + info["coo_nnz"] * (vdt_b + 8) + 16 * N,
-        "hdc": info["ndiag"] * N * vdt_b + info["ndiag"] * 4 + info["csr_nnz"] * (vdt_b + 4) + (N + 1) * 4 + 16 * N,
-    }
-    sel_bytes = bytes_by_fmt[fmt]
+    sel_bytes = alg_bytes(info, N, nnz)
 
     # timed region: K SpMV steps in the selected format
     log(f"[bench] timed region: {args.steps} SpMV steps in {fmt}")
@@ -557,6 +581,7 @@ def main():
         "fixed_csr": {"gbps": round(csr_bytes / (csr_avg * 1e-6) / 1e9, 2), "avg_us": round(csr_avg, 3),
                       "bytes": int(csr_bytes)},
         "speedup_vs_fixed_csr": round(csr_avg / avg_us, 3),
+        "csr_equivalent_gbps": round(csr_bytes / (avg_us * 1e-6) / 1e9, 2),
         "select": sel,
         "copy_probe": copy,
         "stream_ceilings": ceil,
