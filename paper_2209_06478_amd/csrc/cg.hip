@@ -71,7 +71,10 @@ __global__ void __launch_bounds__(CGB) k_cg_dot_pq(i64 n, const X *p, const X *q
     }
 }
 
-template <class X>
+// NT: x and q are streamed (x is not read again until the next update, q
+// not before the next SpMV rewrites it), so they need not displace the
+// matrix lines the next SpMV may still find in the Infinity Cache.
+template <class X, bool NT>
 __global__ void __launch_bounds__(CGB) k_cg_update_xr(i64 n, X *x, X *r, const X *p, const X *q,
                                                        const double *part_pq, int npq, double *part_rr,
                                                        CgState *st) {
@@ -91,8 +94,8 @@ __global__ void __launch_bounds__(CGB) k_cg_update_xr(i64 n, X *x, X *r, const X
     const X a = (X)alpha;
     double acc = 0;
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
-        x[i] = x[i] + a * p[i];
-        X ri = r[i] - a * q[i];
+        st_stream<X, NT>(x + i, ld_stream<X, NT>(x + i) + a * p[i]);
+        X ri = r[i] - a * ld_stream<X, NT>(q + i);
         r[i] = ri;
         acc += (double)ri * (double)ri;
     }
@@ -103,7 +106,7 @@ __global__ void __launch_bounds__(CGB) k_cg_update_xr(i64 n, X *x, X *r, const X
     }
 }
 
-template <class X>
+template <class X, bool NT>
 __global__ void __launch_bounds__(CGB) k_cg_update_p(i64 n, const X *r, X *p, const double *part_rr, CgState *st) {
     __shared__ double lds[CGB / WAVE];
     if (wg_done(&st->done)) return;
@@ -123,7 +126,7 @@ __global__ void __launch_bounds__(CGB) k_cg_update_p(i64 n, const X *r, X *p, co
     if (done) return;
     const X beta = (X)(rho1 / rho);
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
-        p[i] = r[i] + beta * p[i];
+        p[i] = ld_stream<X, NT>(r + i) + beta * p[i];
 }
 
 // ---------------------------------------------------------------- IR helpers
@@ -531,6 +534,11 @@ static CgBuffers cg_buffers(dsm_matrix m, bool ir, Workspace &cgws) {
 
 static unsigned vec_grid(i64 n) { return (unsigned)std::max<i64>(1, std::min<i64>(CGG, (n + CGB - 1) / CGB)); }
 
+static bool cg_stream_vectors() {
+    const char *e = getenv("DSM_CG_NT");
+    return e && e[0] == '1';
+}
+
 // One CG iteration: SpMV with p.q, x/r update, p update (DIA/ELL sweeps
 // write the p.q partials themselves; other formats take a separate dot
 // kernel).  Every kernel checks the state's done flag first, so iterations
@@ -545,8 +553,15 @@ static void enqueue_iteration(dsm_matrix m, X *x, X *r, X *p, X *q, double *part
         hipLaunchKernelGGL((k_cg_dot_pq<X>), dim3(CGG), dim3(CGB), 0, s, n, p, q, part_a, st);
         npq = CGG;
     }
-    hipLaunchKernelGGL((k_cg_update_xr<X>), dim3(CGG), dim3(CGB), 0, s, n, x, r, p, q, part_a, npq, part_b, st);
-    hipLaunchKernelGGL((k_cg_update_p<X>), dim3(CGG), dim3(CGB), 0, s, n, r, p, part_b, st);
+    if (cg_stream_vectors()) {
+        hipLaunchKernelGGL((k_cg_update_xr<X, true>), dim3(CGG), dim3(CGB), 0, s, n, x, r, p, q, part_a, npq, part_b,
+                           st);
+        hipLaunchKernelGGL((k_cg_update_p<X, true>), dim3(CGG), dim3(CGB), 0, s, n, r, p, part_b, st);
+    } else {
+        hipLaunchKernelGGL((k_cg_update_xr<X, false>), dim3(CGG), dim3(CGB), 0, s, n, x, r, p, q, part_a, npq,
+                           part_b, st);
+        hipLaunchKernelGGL((k_cg_update_p<X, false>), dim3(CGG), dim3(CGB), 0, s, n, r, p, part_b, st);
+    }
 }
 
 bool cg_graphs_enabled() {

@@ -119,6 +119,13 @@ __device__ __forceinline__ bf16 ld_stream<bf16, true>(const bf16 *p) {
     return r;
 }
 
+// Store of a value that no kernel before the next pass over it reads again.
+template <class V, bool NT>
+__device__ __forceinline__ void st_stream(V *p, V v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 inline size_t dtype_size(int dt) { return dt == DSM_F64 ? 8 : dt == DSM_F32 ? 4 : 2; }
 inline const char *format_name(int f) {
     static const char *n[] = {"COO", "CSR", "DIA", "ELL", "HYB", "HDC"};

@@ -106,8 +106,10 @@ __global__ void __launch_bounds__(MB) k_symgs_csr(i64 cnt, const i32 *__restrict
                 v[u] = k < e1 ? val[k] : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < U; u++)
-                if (c[u] != i) s += v[u] * x[c[u]];
+            for (int u = 0; u < U; u++) {
+                const double xv = x[c[u]];  // c[u] is in range (i for padding)
+                s += c[u] != i ? v[u] * xv : 0.0;
+            }
         }
     }
     s = group_sum<W>(s);
@@ -127,24 +129,31 @@ __global__ void __launch_bounds__(MB) k_symgs_dia(i64 t0, i64 cnt, const i32 *__
     if (stopped(stop)) return;
     // R rows per thread, each with its own sum, and the diagonal loop
     // unrolled: several independent loads in flight per thread
+    // Loads are unconditional, at clamped in-range addresses, and the
+    // products of out-of-range or diagonal slots are selected away: no load
+    // sits behind a branch, so the unrolled iterations' loads are all in
+    // flight together instead of one round trip per diagonal.
     const i64 g0 = (i64)blockIdx.x * MB * R + threadIdx.x;
-    i64 i[R];
+    i64 i[R], gq[R];
     double s[R];
 #pragma unroll
     for (int q = 0; q < R; q++) {
         const i64 g = g0 + (i64)q * MB;
+        gq[q] = g < cnt ? g : 0;
         i[q] = g < cnt ? rows[t0 + g] : -1;
         s[q] = 0;
     }
-#pragma unroll 9
+#pragma unroll 27
     for (i64 k = 0; k < ndiag; k++) {
         const i64 off = offs[k];
-        if (off == 0) continue;
         const double *dk = dperm + k * pitch + t0;
 #pragma unroll
         for (int q = 0; q < R; q++) {
             const i64 j = i[q] + off;
-            if (i[q] >= 0 && j >= 0 && j < n) s[q] += dk[g0 + (i64)q * MB] * x[j];
+            const bool ok = off != 0 && i[q] >= 0 && j >= 0 && j < n;
+            const double v = dk[gq[q]];
+            const double xv = x[ok ? j : 0];
+            s[q] += ok ? v * xv : 0.0;
         }
     }
 #pragma unroll
@@ -185,7 +194,10 @@ __global__ void __launch_bounds__(SBT) k_symgs_dia_block(int nc, const i64 *__re
             for (i64 k = 0; k < ndiag; k++) {
                 const i64 off = offs[k];
                 const i64 j = i + off;
-                if (off != 0 && j >= 0 && j < n) s += dperm[k * pitch + t] * x[j];
+                const bool ok = off != 0 && j >= 0 && j < n;
+                const double v = dperm[k * pitch + t];
+                const double xv = x[ok ? j : 0];
+                s += ok ? v * xv : 0.0;
             }
             x[i] = (r[i] - s) / diag[i];
         }
@@ -217,7 +229,8 @@ __global__ void __launch_bounds__(SBT) k_symgs_csr_block(int nc, const i64 *__re
                 const i64 e1 = rp[i + 1];
                 for (i64 k = rp[i] + lane; k < e1; k += W) {
                     const i32 cc = col[k];
-                    if (cc != i) s += val[k] * x[cc];
+                    const double v = val[k], xv = x[cc];
+                    s += cc != i ? v * xv : 0.0;
                 }
             }
             s = group_sum<W>(s);

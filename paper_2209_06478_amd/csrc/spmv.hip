@@ -190,6 +190,10 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
     for (int r = 0; r < R; r++)
 #pragma unroll
         for (int w = 0; w < RW; w++) s[r][w] = 0;
+    // Every load is unconditional at an in-range address (slot 0 / x[0]
+    // stand in for rows past the end and for columns outside the matrix; a
+    // matrix with a diagonal has ncols > 0) and the out-of-range products are
+    // selected away, so no load waits behind a branch.
     for (i64 k = 0; k < ndiag; k++) {
         const i64 off = offs[k];
         const V *dk = dval + k * pitch;
@@ -197,16 +201,21 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
         for (int r = 0; r < R; r++) {
             const i64 i = i0 + (i64)r * SB * RW;
             const i64 j = i + off;
+            const bool in = i < nrows;
             if constexpr (P2) {
                 // i is even and the pitch a multiple of 64, so the pair is
                 // aligned; slot i + 1 < pitch always exists (padding is 0)
-                if (i < nrows) {
-                    const pair2<V> v = *(const pair2<V> *)(dk + i);
-                    if (j >= 0 && j < ncols) s[r][0] += widen<X>(v.a) * x[j];
-                    if (i + 1 < nrows && j + 1 >= 0 && j + 1 < ncols) s[r][1] += widen<X>(v.b) * x[j + 1];
-                }
+                const pair2<V> v = *(const pair2<V> *)(dk + (in ? i : 0));
+                const bool ok0 = in && j >= 0 && j < ncols;
+                const bool ok1 = i + 1 < nrows && j + 1 >= 0 && j + 1 < ncols;
+                const X x0 = x[ok0 ? j : 0], x1 = x[ok1 ? j + 1 : 0];
+                s[r][0] += ok0 ? widen<X>(v.a) * x0 : (X)0;
+                s[r][1] += ok1 ? widen<X>(v.b) * x1 : (X)0;
             } else {
-                if (i < nrows && j >= 0 && j < ncols) s[r][0] += widen<X>(dk[i]) * x[j];
+                const bool ok = in && j >= 0 && j < ncols;
+                const V v = dk[in ? i : 0];
+                const X xv = x[ok ? j : 0];
+                s[r][0] += ok ? widen<X>(v) * xv : (X)0;
             }
         }
     }
@@ -234,24 +243,36 @@ __global__ void __launch_bounds__(SB) k_ell(i64 nrows, i64 K, i64 pitch, const i
     for (int r = 0; r < R; r++)
 #pragma unroll
         for (int w = 0; w < RW; w++) s[r][w] = 0;
+    // As in the DIA sweep: unconditional loads at in-range addresses
+    // (x[0] for padding slots: a matrix with K > 0 has ncols > 0), products
+    // of padding selected away.
     for (i64 k = 0; k < K; k++) {
 #pragma unroll
         for (int r = 0; r < R; r++) {
             const i64 i = i0 + (i64)r * SB * RW;
             if constexpr (P2) {
-                // rows i (even) and i + 1; slots past nrows are never read
+                // rows i (even) and i + 1; slots of rows past nrows are never
+                // read (the pair load needs both rows, a last odd row is read
+                // alone)
                 if (i + 1 < nrows) {
                     const pair2<i32> c = *(const pair2<i32> *)(ecol + k * pitch + i);
                     const pair2<V> v = *(const pair2<V> *)(evl + k * pitch + i);
-                    if (c.a >= 0) s[r][0] += widen<X>(v.a) * x[c.a];
-                    if (c.b >= 0) s[r][1] += widen<X>(v.b) * x[c.b];
+                    const X x0 = x[c.a >= 0 ? c.a : 0], x1 = x[c.b >= 0 ? c.b : 0];
+                    s[r][0] += c.a >= 0 ? widen<X>(v.a) * x0 : (X)0;
+                    s[r][1] += c.b >= 0 ? widen<X>(v.b) * x1 : (X)0;
                 } else if (i < nrows) {
                     const i32 c = ecol[k * pitch + i];
-                    if (c >= 0) s[r][0] += widen<X>(evl[k * pitch + i]) * x[c];
+                    const V v = evl[k * pitch + i];
+                    const X xv = x[c >= 0 ? c : 0];
+                    s[r][0] += c >= 0 ? widen<X>(v) * xv : (X)0;
                 }
-            } else if (i < nrows) {
-                const i32 c = ecol[k * pitch + i];
-                if (c >= 0) s[r][0] += widen<X>(evl[k * pitch + i]) * x[c];
+            } else {
+                const i64 ii = i < nrows ? i : 0;
+                const i32 c0 = ecol[k * pitch + ii];
+                const i32 c = i < nrows ? c0 : -1;
+                const V v = evl[k * pitch + ii];
+                const X xv = x[c >= 0 ? c : 0];
+                s[r][0] += c >= 0 ? widen<X>(v) * xv : (X)0;
             }
         }
     }
