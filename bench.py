@@ -25,7 +25,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # (workload, format, kernel variant).  Source: profiles/dia_spmv_hpcg104.md.
 # An entry is removed when its kernel changes.
 PROFILED_TRAFFIC = {
+    ("hpcg27_104", "dia", 4): 261164599,
     ("hpcg27_104", "dia", 8): 266839979,
+    ("hpcg27_104", "dia", 10): 266196775,
 }
 
 
