@@ -82,12 +82,17 @@ namespace dsm {
 // ---------------------------------------------------------------- kernels
 __device__ __forceinline__ bool stopped(const int *stop) { return stop && *(volatile const int *)stop; }
 
+// The multi-launch kernels below read the done flag at their start but test
+// it only before their stores, so the flag's load overlaps the kernel's own
+// loads instead of adding a round trip (the flag is written only by other
+// launches, so every thread sees the same value).
+
 template <int W>
 __global__ void __launch_bounds__(MB) k_symgs_csr(i64 cnt, const i32 *__restrict__ rows, const i32 *__restrict__ rp,
                                                   const i32 *__restrict__ col, const double *__restrict__ val,
                                                   const double *__restrict__ diag, const double *__restrict__ r,
                                                   double *__restrict__ x, const int *stop) {
-    if (stopped(stop)) return;  // the flag is written only by other launches
+    const bool halt = stopped(stop);
     constexpr int U = 4;        // entries a lane loads before its x gathers
     const i64 g = ((i64)blockIdx.x * MB + threadIdx.x) / W;
     const int lane = threadIdx.x % W;
@@ -113,7 +118,7 @@ __global__ void __launch_bounds__(MB) k_symgs_csr(i64 cnt, const i32 *__restrict
         }
     }
     s = group_sum<W>(s);
-    if (g < cnt && lane == 0) x[i] = (r[i] - s) / diag[i];
+    if (g < cnt && lane == 0 && !halt) x[i] = (r[i] - s) / diag[i];
 }
 
 // DIA levels keep a colour-ordered copy of the diagonals: slot t of
@@ -126,7 +131,7 @@ __global__ void __launch_bounds__(MB) k_symgs_dia(i64 t0, i64 cnt, const i32 *__
                                                   i64 pitch, const double *__restrict__ diag,
                                                   const double *__restrict__ r, double *__restrict__ x,
                                                   const int *stop) {
-    if (stopped(stop)) return;
+    const bool halt = stopped(stop);
     // R rows per thread, each with its own sum, and the diagonal loop
     // unrolled: several independent loads in flight per thread
     // Loads are unconditional, at clamped in-range addresses, and the
@@ -158,7 +163,7 @@ __global__ void __launch_bounds__(MB) k_symgs_dia(i64 t0, i64 cnt, const i32 *__
     }
 #pragma unroll
     for (int q = 0; q < R; q++)
-        if (i[q] >= 0) x[i[q]] = (r[i[q]] - s[q]) / diag[i[q]];
+        if (i[q] >= 0 && !halt) x[i[q]] = (r[i[q]] - s[q]) / diag[i[q]];
 }
 
 __global__ void k_dia_colour_order(i64 n, i64 ndiag, const double *__restrict__ dval, i64 pitch,
@@ -241,30 +246,31 @@ __global__ void __launch_bounds__(SBT) k_symgs_csr_block(int nc, const i64 *__re
 }
 
 __global__ void k_mg_zero(i64 n, double *x, const int *stop) {
-    if (stopped(stop)) return;
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = 0.0;
+    if (i < n && !stopped(stop)) x[i] = 0.0;
 }
 
 // rc = (r - A x) at the coarse points
 __global__ void k_restrict(i64 nc, const i32 *__restrict__ f2c, const double *__restrict__ r,
                            const double *__restrict__ ax, double *__restrict__ rc, const int *stop) {
-    if (stopped(stop)) return;
+    const bool halt = stopped(stop);
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nc) {
         const i32 f = f2c[i];
-        rc[i] = r[f] - ax[f];
+        const double v = r[f] - ax[f];
+        if (!halt) rc[i] = v;
     }
 }
 
 // x += xc at the coarse points (f2c is injective)
 __global__ void k_prolong(i64 nc, const i32 *__restrict__ f2c, const double *__restrict__ xc, double *__restrict__ x,
                           const int *stop) {
-    if (stopped(stop)) return;
+    const bool halt = stopped(stop);
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nc) {
         const i32 f = f2c[i];
-        x[f] = x[f] + xc[i];
+        const double v = x[f] + xc[i];
+        if (!halt) x[f] = v;
     }
 }
 
