@@ -32,7 +32,7 @@ template <class X>
 __global__ void __launch_bounds__(CGB) k_cg_init(i64 n, const X *b, const X *q, X *r, X *p, double *part) {
     __shared__ double lds[CGB / WAVE];
     double acc = 0;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x) {
         X ri = b[i] - q[i];
         r[i] = ri;
         p[i] = ri;
@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(CGB) k_cg_dot_pq(i64 n, const X *p, const X *q
     __shared__ double lds[CGB / WAVE];
     if (wg_done(&st->done)) return;
     double acc = 0;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x)
         acc += (double)p[i] * (double)q[i];
     acc = block_sum(acc, lds);
     if (threadIdx.x == 0) {
@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(CGB) k_cg_update_xr(i64 n, X *x, X *r, const X
     const double alpha = rho / pq;
     const X a = (X)alpha;
     double acc = 0;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x) {
         st_stream<X, NT>(x + i, ld_stream<X, NT>(x + i) + a * p[i]);
         X ri = r[i] - a * ld_stream<X, NT>(q + i);
         r[i] = ri;
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(CGB) k_cg_update_p(i64 n, const X *r, X *p, co
     }
     if (done) return;
     const X beta = (X)(rho1 / rho);
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x)
         p[i] = ld_stream<X, NT>(r + i) + beta * p[i];
 }
 
@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(CGB) k_residual(i64 n, const double *b, const 
                                                   double *part_bb) {
     __shared__ double lds[CGB / WAVE];
     double a = 0, c = 0;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x) {
         double ri = b[i] - q[i];
         r[i] = ri;
         a += ri * ri;
@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(CGB) k_norms(const double *part_rr, const doub
 // r32 = r / ||r|| (FP32), d32 = 0
 __global__ void __launch_bounds__(CGB) k_scale_down(i64 n, const double *r, const double *nrm, float *r32, float *d32) {
     const double inv = nrm[0] > 0 ? 1.0 / nrm[0] : 0.0;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x) {
         r32[i] = (float)(r[i] * inv);
         d32[i] = 0.0f;
     }
@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(CGB) k_scale_down(i64 n, const double *r, cons
 // x += ||r|| * d32 (FP64)
 __global__ void __launch_bounds__(CGB) k_apply_update(i64 n, double *x, const float *d32, const double *nrm) {
     const double s = nrm[0];
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x)
         x[i] = x[i] + s * (double)d32[i];
 }
 
@@ -196,7 +196,7 @@ __device__ __forceinline__ X p_next(X r, X pold, X beta, bool first) {
     return first ? r : fma(beta, pold, r);
 }
 
-template <class V, class X, int R, bool XCD, bool NT, bool ELL>
+template <class V, class X, int R, bool XCD, bool ELL>
 __global__ void __launch_bounds__(256) k_cgf_spmv(i64 n, i64 nd, const i32 *__restrict__ offs,
                                                   const i32 *__restrict__ ecol, const V *__restrict__ vals, i64 pitch,
                                                   const X *__restrict__ r, const X *__restrict__ pold,
@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(256) k_cgf_spmv(i64 n, i64 nd, const i32 *__re
                 const i64 i = i0 + (i64)t * 256;
                 const i64 j = i + off;
                 if (i < n && j >= 0 && j < n) {
-                    const V v = ld_stream<V, NT>(dk + i);
+                    const V v = dk[i];
                     s[t] += widen<X>(v) * p_next<X>(r[j], pold[j], beta, first);
                 }
             }
@@ -286,7 +286,7 @@ __global__ void __launch_bounds__(CGB) k_cgf_update(i64 n, X *x, X *r, const X *
     }
     const X a = (X)(rho / pq);
     double acc = 0;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x) {
         x[i] = x[i] + a * p[i];
         const X ri = r[i] - a * q[i];
         r[i] = ri;
@@ -320,28 +320,28 @@ static int fused_groups(const dsm_matrix_s *m) {
     return (int)grid_for(m->nrows, 256 * R);
 }
 
-template <class V, class X, int R, bool XCD, bool NT>
+template <class V, class X, int R, bool XCD>
 static void cgf_launch(dsm_matrix m, const X *r, const X *pold, X *pnew, X *q, double *part_rr, double *part_pq,
                        CgState *st, int ph, hipStream_t s) {
     const Payload &P = m->P;
     const i64 n = m->nrows;
     const unsigned g = grid_for(n, 256 * R);
     if (P.fmt == DSM_DIA)
-        hipLaunchKernelGGL((k_cgf_spmv<V, X, R, XCD, NT, false>), dim3(g), dim3(256), 0, s, n, P.ndiag, P.offs,
+        hipLaunchKernelGGL((k_cgf_spmv<V, X, R, XCD, false>), dim3(g), dim3(256), 0, s, n, P.ndiag, P.offs,
                            (const i32 *)nullptr, (const V *)P.dval, P.pitch, r, pold, pnew, q, part_rr, part_pq, st,
                            ph);
     else
-        hipLaunchKernelGGL((k_cgf_spmv<V, X, R, XCD, NT, true>), dim3(g), dim3(256), 0, s, n, P.K,
+        hipLaunchKernelGGL((k_cgf_spmv<V, X, R, XCD, true>), dim3(g), dim3(256), 0, s, n, P.K,
                            (const i32 *)nullptr, P.ecol, (const V *)P.evl, P.pitch, r, pold, pnew, q, part_rr,
                            part_pq, st, ph);
 }
 
-template <class V, class X, bool XCD, bool NT>
+template <class V, class X, bool XCD>
 static void cgf_r(dsm_matrix m, int lr, const X *r, const X *pold, X *pnew, X *q, double *prr, double *ppq,
                   CgState *st, int ph, hipStream_t s) {
-    if (lr == 0) cgf_launch<V, X, 1, XCD, NT>(m, r, pold, pnew, q, prr, ppq, st, ph, s);
-    else if (lr == 1) cgf_launch<V, X, 2, XCD, NT>(m, r, pold, pnew, q, prr, ppq, st, ph, s);
-    else cgf_launch<V, X, 4, XCD, NT>(m, r, pold, pnew, q, prr, ppq, st, ph, s);
+    if (lr == 0) cgf_launch<V, X, 1, XCD>(m, r, pold, pnew, q, prr, ppq, st, ph, s);
+    else if (lr == 1) cgf_launch<V, X, 2, XCD>(m, r, pold, pnew, q, prr, ppq, st, ph, s);
+    else cgf_launch<V, X, 4, XCD>(m, r, pold, pnew, q, prr, ppq, st, ph, s);
 }
 
 template <class V, class X>
@@ -352,8 +352,8 @@ static void cgf_dispatch(dsm_matrix m, const X *r, const X *pold, X *pnew, X *q,
     const int v = m->variant;
     const bool xcd = !(v & 1);
     const int lr = (v >> 1) & 3;
-    if (xcd) cgf_r<V, X, true, false>(m, lr, r, pold, pnew, q, prr, ppq, st, ph, s);
-    else cgf_r<V, X, false, false>(m, lr, r, pold, pnew, q, prr, ppq, st, ph, s);
+    if (xcd) cgf_r<V, X, true>(m, lr, r, pold, pnew, q, prr, ppq, st, ph, s);
+    else cgf_r<V, X, false>(m, lr, r, pold, pnew, q, prr, ppq, st, ph, s);
 }
 
 // One fused iteration with parity ph; p buffers alternate: p[ph] is written.
@@ -387,7 +387,7 @@ __global__ void __launch_bounds__(CGB) k_pcg_init(i64 n, const double *b, const 
                                                   double *r, double *p, double *part_rz, double *part_rr) {
     __shared__ double lds[CGB / WAVE];
     double rz = 0, rr = 0;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x) {
         const double ri = b[i] - q[i];
         const double zi = ri * dinv[i];
         r[i] = ri;
@@ -438,7 +438,7 @@ __global__ void __launch_bounds__(CGB) k_pcg_update_xr(i64 n, double *x, double 
     }
     const double alpha = rho / pq;
     double rz = 0, rr = 0;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x) {
         x[i] = x[i] + alpha * p[i];
         const double ri = r[i] - alpha * q[i];
         r[i] = ri;
@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(CGB) k_pcg_update_p(i64 n, const double *r, do
     }
     if (done) return;
     const double beta = rho1 / rho;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x)
         p[i] = r[i] * dinv[i] + beta * p[i];
 }
 

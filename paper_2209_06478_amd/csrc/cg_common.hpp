@@ -25,6 +25,17 @@ struct CgState {
     int pad;
 };
 
+// Contiguous slice [slice_lo(n), slice_hi(n)) of [0, n) for this workgroup,
+// a whole number of blockDim.x-element rows long: each workgroup of a
+// vector kernel streams one run of consecutive elements, which keeps DRAM
+// pages open (a grid-stride walk streamed about 10% slower on MI355X).
+__device__ __forceinline__ i64 slice_len(i64 n) {
+    const i64 per = (n + gridDim.x - 1) / gridDim.x;
+    return (per + blockDim.x - 1) / blockDim.x * blockDim.x;
+}
+__device__ __forceinline__ i64 slice_lo(i64 n) { return min((i64)blockIdx.x * slice_len(n), n); }
+__device__ __forceinline__ i64 slice_hi(i64 n) { return min(slice_lo(n) + slice_len(n), n); }
+
 // Every workgroup reduces the same `count` partials in the same order.
 __device__ __forceinline__ double reduce_partials(const double *part, double *lds, int count = CGG) {
     double v = 0;

@@ -308,7 +308,7 @@ __global__ void k_count_bad_diag(i64 n, const double *d, int *bad) {
 __global__ void __launch_bounds__(CGB) k_pmg_init(i64 n, const double *b, const double *ax, double *r, double *part) {
     __shared__ double lds[CGB / WAVE];
     double acc = 0;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x) {
         const double ri = b[i] - ax[i];
         r[i] = ri;
         acc += ri * ri;
@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(CGB) k_pmg_norms(i64 n, const double *b, const
                                                    double *part_bb) {
     __shared__ double lds[CGB / WAVE];
     double rr = 0, bb = 0;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x) {
         const double ri = b[i] - ax[i];
         rr += ri * ri;
         bb += b[i] * b[i];
@@ -355,7 +355,7 @@ __global__ void __launch_bounds__(CGB) k_pmg_rz(i64 n, const double *r, const do
     __shared__ double lds[CGB / WAVE];
     if (wg_done(&st->done)) return;
     double acc = 0;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x)
         acc += r[i] * z[i];
     acc = block_sum(acc, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
@@ -372,7 +372,7 @@ __global__ void __launch_bounds__(CGB) k_pmg_update_p(i64 n, const double *z, do
     if (blockIdx.x == 0 && threadIdx.x == 0) st->rho[k & 1] = rz;
     const bool first = k == 0;
     const double beta = first ? 0.0 : rz / st->rho[(k & 1) ^ 1];
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x)
         p[i] = first ? z[i] : z[i] + beta * p[i];
 }
 
@@ -393,7 +393,7 @@ __global__ void __launch_bounds__(CGB) k_pmg_update_xr(i64 n, double *x, double 
     }
     const double alpha = rho / pq;
     double acc = 0;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x) {
         x[i] = x[i] + alpha * p[i];
         const double ri = r[i] - alpha * q[i];
         r[i] = ri;
@@ -425,7 +425,7 @@ __global__ void __launch_bounds__(CGB) k_pmg_dot_pq(i64 n, const X *p, const X *
     __shared__ double lds[CGB / WAVE];
     if (wg_done(&st->done)) return;
     double acc = 0;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x)
         acc += (double)p[i] * (double)q[i];
     acc = block_sum(acc, lds);
     if (threadIdx.x == 0) {

@@ -10,7 +10,7 @@
 //        (fewer than 2*1024, coalesced) into LDS as products, then reduces
 //        each row with a power-of-two group of lanes; a row longer than 1024
 //        entries gets a workgroup of its own.  Vector variants assign W lanes
-//        to each row (row blocks in XCD-aware order).
+//        to each row.
 //   DIA  one thread per row sweeps the diagonals; the diagonal-major layout
 //        makes every value load and every x load contiguous across a wave.
 //   ELL  one thread per row sweeps the K slots (column-major, coalesced).
@@ -116,10 +116,10 @@ __global__ void __launch_bounds__(SB) k_csr_vector(i64 nrows, const i32 *__restr
                                                    const V *__restrict__ val, const X *__restrict__ x,
                                                    X *__restrict__ y, const int *__restrict__ stop) {
     if (stop && *stop) return;
-    // XCD-aware tile order: neighbouring row blocks share x lines, so they
-    // should share an L2 (round-robin placement would fetch them into all 8)
-    const u32 b = xcd_tile(blockIdx.x, gridDim.x);
-    const i64 row = ((i64)b * SB + threadIdx.x) / W;
+    // launch order, not the XCD-aware order: with it the HPCG 104^3 launch
+    // fetched 382 instead of 456 MB (no x lines fetched into several L2s)
+    // but ran 3% slower, this kernel being bound by gather latency
+    const i64 row = ((i64)blockIdx.x * SB + threadIdx.x) / W;
     const int lane = threadIdx.x % W;
     X s = 0;
     if (row < nrows) {
