@@ -20,6 +20,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "admission.hpp"
 #include "core.hpp"
 
 struct dsm_server_s {
@@ -35,15 +36,15 @@ struct dsm_server_s {
         dsm_cg_result res{};
         dsm_timestamps ts{};
     };
+    dsm_server_s(const dsm_server_opts &o, size_t budget_bytes)
+        : opts(o), budget(budget_bytes), adm(o.slots, budget_bytes, o.batch_max) {}
     dsm_ctx ctx = nullptr;
     dsm_server_opts opts{};
     size_t budget = 0;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::deque<uint64_t> queue;
+    dsm::Admission adm;  // queue, slots and budget (guarded by mu)
     std::unordered_map<uint64_t, Req> reqs;
-    size_t bytes_in_flight = 0;
-    int in_flight = 0;
     bool stopping = false;
     uint64_t next_ticket = 1;
     std::vector<std::thread> workers;
@@ -51,9 +52,6 @@ struct dsm_server_s {
 
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    }
-    bool fits(const Req &r) const {
-        return in_flight < opts.slots && (budget == 0 || bytes_in_flight + r.footprint <= budget);
     }
 };
 
@@ -70,34 +68,19 @@ static void worker_main(dsm_server s) {
         {
             std::unique_lock<std::mutex> lk(s->mu);
             for (;;) {
-                if (!s->queue.empty()) {
-                    auto &head = s->reqs[s->queue.front()];
-                    if (s->fits(head)) break;
+                const auto items = s->adm.take(&small);
+                if (!items.empty()) {
+                    const double t = s->now();
+                    for (const auto &it : items) {
+                        s->reqs[it.id].ts.start_s = t;
+                        take.push_back(it.id);
+                    }
+                    break;
                 }
-                if (s->stopping && s->queue.empty()) break;
+                if (s->stopping && s->adm.empty()) break;
                 s->cv_work.wait(lk);
             }
-            if (s->queue.empty()) break;  // stopping and drained
-            const double t = s->now();
-            auto admit = [&](std::deque<uint64_t>::iterator it) {
-                auto &r = s->reqs[*it];
-                s->in_flight++;
-                s->bytes_in_flight += r.footprint;
-                r.ts.start_s = t;
-                take.push_back(*it);
-                return s->queue.erase(it);
-            };
-            small = s->reqs[s->queue.front()].small;
-            admit(s->queue.begin());
-            // a small head takes every queued small request that fits, in
-            // arrival order, not only the run at the head: in a mixed stream
-            // such runs are short and one-request launches leave the GPU idle
-            if (small)
-                for (auto it = s->queue.begin(); it != s->queue.end() && (int)take.size() < s->opts.batch_max;) {
-                    auto &r = s->reqs[*it];
-                    if (r.small && s->fits(r)) it = admit(it);
-                    else ++it;
-                }
+            if (take.empty()) break;  // stopping and drained
         }
         // run outside the lock
         std::vector<dsm_cg_result> res(take.size());
@@ -150,8 +133,7 @@ static void worker_main(dsm_server s) {
                 r.error = err;
                 r.ts.finish_s = t;
                 r.done = true;
-                s->in_flight--;
-                s->bytes_in_flight -= r.footprint;
+                s->adm.release(r.footprint);
             }
         }
         s->cv_done.notify_all();
@@ -186,10 +168,8 @@ DSM_API dsm_status dsm_server_create(dsm_ctx ctx, const dsm_server_opts *opts, d
                   "slots, streams (1..16) and batch_max must be positive");
         DSM_CHECK(o.small_rows >= 0 && o.small_rows <= 40000, DSM_E_INVALID,
                   "small_rows must be in [0, 40000] (the one-workgroup solver's limit)");
-        auto *s = new dsm_server_s();
+        auto *s = new dsm_server_s(o, o.hbm_budget ? o.hbm_budget : ctx->budget);
         s->ctx = ctx;
-        s->opts = o;
-        s->budget = o.hbm_budget ? o.hbm_budget : ctx->budget;
         s->t0 = std::chrono::steady_clock::now();
         for (int i = 0; i < o.streams; i++) s->workers.emplace_back(worker_main, s);
         *out = s;
@@ -220,7 +200,7 @@ DSM_API dsm_status dsm_server_submit(dsm_server s, dsm_matrix m, const double *b
         r.ts.arrival_s = s->now();
         const uint64_t id = s->next_ticket++;
         s->reqs.emplace(id, r);
-        s->queue.push_back(id);
+        s->adm.push(id, r.footprint, r.small);
         *ticket = id;
         s->cv_work.notify_one();
     });

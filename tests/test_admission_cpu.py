@@ -1,0 +1,21 @@
+"""The serving loop's admission queue (pure host logic shared by the
+server) on scripted arrivals, built with g++ under AddressSanitizer and
+UndefinedBehaviorSanitizer."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_admission_scenarios(tmp_path):
+    exe = tmp_path / "admission_driver"
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-Wall", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-o", str(exe), os.path.join(ROOT, "tests", "c", "admission_driver.cpp")]
+    subprocess.check_call(cmd)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stdout[-4000:] + r.stderr[-4000:]
+    assert "admission driver ok" in r.stdout
