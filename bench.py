@@ -187,7 +187,8 @@ def ir_bench(dsm, ctx, torch, dev, n=128):
     return out
 
 
-def serving_bench(dsm, ctx, torch, dev, nreq=10000, load=0.8, seed=0x5E4E, small_rows=40000, poisson=True):
+def serving_bench(dsm, ctx, torch, dev, nreq=10000, load=0.8, seed=0x5E4E, small_rows=4096, poisson=True,
+                  rate=None):
     """Poisson stream of CG solves (tol 1e-8) over a pool of resident
     matrices: 27-point stencils 8^3..96^3 and banded SPD 1k..200k rows."""
     import threading
@@ -210,7 +211,9 @@ def serving_bench(dsm, ctx, torch, dev, nreq=10000, load=0.8, seed=0x5E4E, small
     mats, bvec = [], []
     for p in pool:
         A = dsm.Matrix.from_csr(ctx, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
-        if p.nrows <= 40000:
+        # tuned for the path the server will take: the one-workgroup solver
+        # up to small_rows, the device-wide SpMV above
+        if p.nrows <= small_rows:
             A.select(target=1)
         else:
             A.select()
@@ -263,7 +266,7 @@ def serving_bench(dsm, ctx, torch, dev, nreq=10000, load=0.8, seed=0x5E4E, small
 
     log(f"[bench] serving: saturation run ({nreq} requests at once)")
     sat = run(None)
-    rate = sat["solves_per_s"] * load
+    rate = rate if rate else sat["solves_per_s"] * load
     gaps = -np.log(1.0 - inputs.uniform(seed, 43, np.arange(nreq, dtype=np.uint64))) / rate
     log(f"[bench] serving: Poisson run at {load} x saturation ({rate:.0f}/s)")
     open_loop = run(np.cumsum(gaps)) if poisson else None
@@ -286,7 +289,8 @@ def serving_bench(dsm, ctx, torch, dev, nreq=10000, load=0.8, seed=0x5E4E, small
     for A in list(csr.values()) + mats:
         A.close()
     return {"pool": len(pool), "tol": 1e-8, "small_rows": small_rows, "saturation": sat,
-            "poisson": dict(open_loop, load=load) if open_loop else None, "sequential_fp64_csr": seq}
+            "poisson": dict(open_loop, load=round(rate / sat["solves_per_s"], 3), rate=round(rate, 1))
+            if open_loop else None, "sequential_fp64_csr": seq}
 
 
 def irregular_bench(dsm, ctx, torch, dev):

@@ -355,7 +355,8 @@ typedef struct {
                                 (0 = the context's budget or unlimited)       */
     int32_t streams;         /* HIP streams for large requests (default 4)     */
     int64_t small_rows;      /* requests with at most this many rows go to the
-                                persistent batched kernel (default 40000)     */
+                                persistent batched kernel (default 4096, at
+                                most 40000)                                   */
     int32_t batch_max;       /* max requests per persistent launch (def. 256)  */
 } dsm_server_opts;
 

@@ -374,7 +374,7 @@ def stream_probe(mode, dst, src=None, stream=None):
 class Server:
     """Continuous-batching CG server over one context."""
 
-    def __init__(self, ctx, slots=64, hbm_budget=0, streams=4, small_rows=40000, batch_max=256):
+    def __init__(self, ctx, slots=64, hbm_budget=0, streams=4, small_rows=4096, batch_max=256):
         o = L.ServerOpts()
         lib().dsm_server_opts_default(C.byref(o))
         o.slots, o.hbm_budget, o.streams, o.small_rows, o.batch_max = slots, hbm_budget, streams, small_rows, batch_max

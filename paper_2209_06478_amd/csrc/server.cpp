@@ -154,7 +154,11 @@ DSM_API void dsm_server_opts_default(dsm_server_opts *o) {
     o->slots = 64;
     o->hbm_budget = 0;
     o->streams = 4;
-    o->small_rows = 40000;
+    // one-workgroup batching raises throughput a little (5% at saturation on
+    // the mixed stream) but holds every system of a batch until its slowest
+    // member finishes: past a few thousand rows the device-wide solver's
+    // latency is far lower (p50 1.6 vs 19.5 ms at 400 requests/s)
+    o->small_rows = 4096;
     o->batch_max = 256;
 }
 

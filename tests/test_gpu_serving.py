@@ -42,13 +42,17 @@ def run(server, reqs, probs, mats, torch, dev, one_by_one):
     return out
 
 
-def test_serving_alone_equals_mix_and_budget():
+@pytest.mark.parametrize("small_rows", [None, 40000])
+def test_serving_alone_equals_mix_and_budget(small_rows):
+    """small_rows: the default (only the tiny systems batched) and the
+    one-workgroup solver's limit (every system up to 40,000 rows batched)."""
     torch, dev = torch_dev()
     probs, mats = pool()
     rng = inputs.uniform(77, 1, np.arange(60, dtype=np.uint64))
     reqs = [int(u * len(probs)) for u in rng]
     biggest = max(m.info()["bytes"] for m in mats)
-    srv = dsm.Server(ctx(), slots=8, hbm_budget=int(biggest * 2.5), streams=3)
+    kw = {} if small_rows is None else {"small_rows": small_rows}
+    srv = dsm.Server(ctx(), slots=8, hbm_budget=int(biggest * 2.5), streams=3, **kw)
     log("[serving] mix")
     mix = run(srv, reqs, probs, mats, torch, dev, one_by_one=False)
     log("[serving] alone")
