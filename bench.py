@@ -592,6 +592,9 @@ def main():
         "fixed_csr": {"gbps": round(csr_bytes / (csr_avg * 1e-6) / 1e9, 2), "avg_us": round(csr_avg, 3),
                       "bytes": int(csr_bytes)},
         "speedup_vs_fixed_csr": round(csr_avg / avg_us, 3),
+        # against CSR with its kernel tuned too (the selection's own CSR median)
+        "speedup_vs_tuned_csr": (round(sel["median_us"]["csr"] / sel["median_us"][fmt], 3)
+                                 if sel and sel["status"].get("csr") == 0 and sel["median_us"].get(fmt) else None),
         "csr_equivalent_gbps": round(csr_bytes / (avg_us * 1e-6) / 1e9, 2),
         "select": sel,
         "copy_probe": copy,
