@@ -11,6 +11,16 @@ import oracle
 FORMATS = ["coo", "csr", "dia", "ell", "hyb", "hdc"]
 
 
+@functools.lru_cache(maxsize=None)
+def anchors():
+    """Oracle iteration counts at full sizes (tests/golden/cg_anchors.json,
+    written by tests/golden/make_cg_anchors.py from the oracle)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cg_anchors.json")) as f:
+        return json.load(f)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 

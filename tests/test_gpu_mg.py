@@ -9,7 +9,7 @@ import pytest
 import inputs
 import oracle
 import paper_2209_06478_amd as dsm
-from gpu_common import ctx, log, torch_dev
+from gpu_common import anchors, ctx, log, torch_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -186,6 +186,7 @@ def test_pcg_mg_full_size_dia():
     xh = x.cpu().numpy()
     log(f"[mg] pcg dia 104^3 x4: {res}")
     assert res["status"] == "converged"
+    assert abs(res["iters"] - anchors()["pcg_mg_hpcg27_104_4levels_tol1e-10"]["iters"]) <= 1, res
     assert oracle.true_relres(p.row_ptr, p.col, p.val, p.b, xh) <= 1.5e-10
     assert np.max(np.abs(xh - 1.0)) <= 1e-7
     mg.close()
