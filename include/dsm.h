@@ -7,8 +7,15 @@
  * active state changes through activate()/convert, Sections III-A, III-B
  * and IV-B).  On top of the handle sit SpMV (Section III-D, "multiply"),
  * format selection by timed profiling runs (Section V-E, the naive
- * auto-tuner), and the conjugate-gradient loop of HPCG with the
- * preconditioner disabled (Sections II-B and IV-B).
+ * auto-tuner) or by a cost model (Section VII's future work), and the
+ * conjugate-gradient loop of HPCG with the preconditioner disabled
+ * (Sections II-B and IV-B).  Around them: mixed-precision iterative
+ * refinement, a batched one-workgroup-per-system solver and a serving loop
+ * with HBM-budget admission; diagonal extraction and update with Jacobi
+ * PCG (Sections III-D, IV-B); HPCG's own preconditioner, a multicolour
+ * symmetric Gauss-Seidel multigrid V-cycle (Section II-B); y += A x for a
+ * matrix split into parts (Sections V-A, V-E); and streaming probes that
+ * measure the bandwidth ceiling.
  *
  * Conventions shared by every entry point:
  *   - Indices are int32 (row pointers, rows, columns, offsets); linear slot
