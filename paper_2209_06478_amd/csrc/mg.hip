@@ -16,9 +16,8 @@
 // rows see no changed neighbour), so it is skipped.
 //
 // Levels hold CSR or DIA matrices with FP64 values.  CSR rows are reduced
-// by 8 lanes each, DIA rows by 4 lanes each (a lane per quarter of the
-// diagonals; one thread per row sweeping them in ascending offset order on
-// the one-workgroup coarsest level), over a colour-ordered copy of
+// by 8 lanes each; DIA rows by one thread sweeping the diagonals in
+// ascending offset (ascending column) order, over a colour-ordered copy of
 // the diagonals made at set-up (the smoother's values are read at set-up:
 // later value updates of a DIA level are not seen by the smoother).
 #include <algorithm>
@@ -32,7 +31,7 @@ namespace dsm {
 
 constexpr int MB = 256;      // threads per workgroup
 constexpr int GSW = 8;       // CSR lanes per row in the smoother
-constexpr int GSD = 4;       // DIA lanes per row in the smoother
+constexpr int GSR = 1;       // DIA rows per thread in the smoother
 constexpr int MG_MAX_LEVELS = 8;
 
 }  // namespace dsm
@@ -126,35 +125,45 @@ __global__ void __launch_bounds__(MB) k_symgs_csr(i64 cnt, const i32 *__restrict
 // diagonal k holds A(rows[t], rows[t] + off_k), so a colour's rows are a
 // contiguous, coalesced range of every diagonal (in the natural layout they
 // would be every other slot, wasting half of each line fetched).
-template <int W>
+template <int R>
 __global__ void __launch_bounds__(MB) k_symgs_dia(i64 t0, i64 cnt, const i32 *__restrict__ rows, i64 n, i64 ndiag,
                                                   const i32 *__restrict__ offs, const double *__restrict__ dperm,
                                                   i64 pitch, const double *__restrict__ diag,
                                                   const double *__restrict__ r, double *__restrict__ x,
                                                   const int *stop) {
     const bool halt = stopped(stop);
-    // W lanes per row, lane l taking diagonals l, l + W, ...: a colour of a
-    // large level has only ~2 waves per SIMD at one lane per row, too few to
-    // hide the gather latency.  Loads are unconditional, at clamped in-range
-    // addresses, and the products of out-of-range or diagonal slots are
-    // selected away: no load sits behind a branch, so the unrolled
-    // iterations' loads are all in flight together.
-    const i64 g = ((i64)blockIdx.x * MB + threadIdx.x) / W;
-    const int lane = threadIdx.x % W;
-    const i64 gq = g < cnt ? g : 0;
-    const i64 i = g < cnt ? rows[t0 + g] : -1;
-    double s = 0;
-#pragma unroll 7
-    for (i64 k = lane; k < ndiag; k += W) {
-        const i64 off = offs[k];
-        const i64 j = i + off;
-        const bool ok = off != 0 && i >= 0 && j >= 0 && j < n;
-        const double v = dperm[k * pitch + t0 + gq];
-        const double xv = x[ok ? j : 0];
-        s += ok ? v * xv : 0.0;
+    // R rows per thread, each with its own sum, and the diagonal loop
+    // unrolled: several independent loads in flight per thread
+    // Loads are unconditional, at clamped in-range addresses, and the
+    // products of out-of-range or diagonal slots are selected away: no load
+    // sits behind a branch, so the unrolled iterations' loads are all in
+    // flight together instead of one round trip per diagonal.
+    const i64 g0 = (i64)blockIdx.x * MB * R + threadIdx.x;
+    i64 i[R], gq[R];
+    double s[R];
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+        const i64 g = g0 + (i64)q * MB;
+        gq[q] = g < cnt ? g : 0;
+        i[q] = g < cnt ? rows[t0 + g] : -1;
+        s[q] = 0;
     }
-    s = group_sum<W>(s);
-    if (i >= 0 && lane == 0 && !halt) x[i] = (r[i] - s) / diag[i];
+#pragma unroll 27
+    for (i64 k = 0; k < ndiag; k++) {
+        const i64 off = offs[k];
+        const double *dk = dperm + k * pitch + t0;
+#pragma unroll
+        for (int q = 0; q < R; q++) {
+            const i64 j = i[q] + off;
+            const bool ok = off != 0 && i[q] >= 0 && j >= 0 && j < n;
+            const double v = dk[gq[q]];
+            const double xv = x[ok ? j : 0];
+            s[q] += ok ? v * xv : 0.0;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < R; q++)
+        if (i[q] >= 0 && !halt) x[i[q]] = (r[i[q]] - s[q]) / diag[i[q]];
 }
 
 __global__ void k_dia_colour_order(i64 n, i64 ndiag, const double *__restrict__ dval, i64 pitch,
@@ -493,7 +502,7 @@ static void symgs(dsm_mg_s *mg, int l, const double *r, double *x, hipStream_t s
             hipLaunchKernelGGL(k_symgs_csr<GSW>, dim3(grid_for(cnt * GSW, MB)), dim3(MB), 0, s, cnt, lv.rows + c0,
                                P.rp, P.col, (const double *)P.val, lv.diag, r, x, stop);
         else
-            hipLaunchKernelGGL(k_symgs_dia<GSD>, dim3(grid_for(cnt * GSD, MB)), dim3(MB), 0, s, c0, cnt, lv.rows,
+            hipLaunchKernelGGL(k_symgs_dia<GSR>, dim3(grid_for(cnt, MB * GSR)), dim3(MB), 0, s, c0, cnt, lv.rows,
                                lv.n, P.ndiag, P.offs, lv.dperm, P.pitch, lv.diag, r, x, stop);
     };
     for (int c = 0; c < nc; c++) colour(c);
