@@ -22,12 +22,16 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 # HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy of known size; keyed by
-# (workload, format, kernel variant).  Source: profiles/dia_spmv_hpcg104.md.
+# (workload, format, kernel variant).  Source: profiles/dia_spmv_hpcg104.md and
+# profiles/hdc_spmv_hpcg104.md.
 # An entry is removed when its kernel changes.
 PROFILED_TRAFFIC = {
     ("hpcg27_104", "dia", 4): 261164599,
     ("hpcg27_104", "dia", 8): 266839979,
     ("hpcg27_104", "dia", 10): 266196775,
+    ("hpcg27_104", "dia", 0): 262260746,
+    ("hpcg27_104", "hdc", 10): 266213878,
+    ("hpcg27_104", "hdc", 8): 266878854,
 }
 
 
