@@ -61,10 +61,20 @@ void *ws_get(dsm_ctx ctx, Workspace &w, size_t bytes) {
     return w.p;
 }
 
-void ws_release(dsm_ctx ctx, Workspace &w) {
+void ws_release_host(Workspace &w) {
     drop_graph(w);
     if (w.stream) (void)hipStreamDestroy(w.stream);
     w.stream = nullptr;
+    for (auto &e : w.events) {
+        if (e) (void)hipEventDestroy((hipEvent_t)e);
+        e = nullptr;
+    }
+    if (w.host) (void)hipHostFree(w.host);
+    w.host = nullptr;
+}
+
+void ws_release(dsm_ctx ctx, Workspace &w) {
+    ws_release_host(w);
     if (w.p) dev_free(ctx, w.p, w.bytes);
     w.p = nullptr;
     w.bytes = 0;

@@ -72,6 +72,13 @@ __global__ void __launch_bounds__(CGB) k_cg_dot_pq(i64 n, const X *p, const X *q
     }
 }
 
+constexpr int VU = 4;  // elements per lane per pass in the vector updates
+
+// The vector updates load their first VU elements per lane before they
+// reduce the partials their scalar depends on (the loads do not need it), so
+// the latency of the reduction and of the first stream overlap; every load
+// of a pass is issued before any of its stores.
+//
 // NT: x and q are streamed (x is not read again until the next update, q
 // not before the next SpMV rewrites it), so they need not displace the
 // matrix lines the next SpMV may still find in the Infinity Cache.
@@ -80,10 +87,27 @@ __global__ void __launch_bounds__(CGB) k_cg_update_xr(i64 n, X *x, X *r, const X
                                                        const double *part_pq, int npq, double *part_rr,
                                                        CgState *st) {
     __shared__ double lds[CGB / WAVE];
-    if (wg_done(&st->done)) return;
-    const double pq = reduce_partials(part_pq, lds, npq);
+    const i64 hi = slice_hi(n);
+    i64 base = slice_lo(n) + threadIdx.x;
+    X xv[VU], pv[VU], rv[VU], qv[VU];
+    auto load = [&]() {
+#pragma unroll
+        for (int u = 0; u < VU; u++) {
+            const i64 i = base + (i64)u * blockDim.x;
+            if (i < hi) {
+                xv[u] = ld_stream<X, NT>(x + i);
+                pv[u] = p[i];
+                rv[u] = r[i];
+                qv[u] = ld_stream<X, NT>(q + i);
+            }
+        }
+    };
+    load();
     const long long k = st->iters;
-    const double rho = st->rho[(k - 1) & 1];
+    const double rho_even = st->rho[0], rho_odd = st->rho[1];
+    double pq;
+    if (wg_done_sum(&st->done, part_pq, npq, lds, &pq)) return;
+    const double rho = ((k - 1) & 1) ? rho_odd : rho_even;
     if (!(pq > 0) || !isfinite(pq)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st->pq = pq;
@@ -91,14 +115,21 @@ __global__ void __launch_bounds__(CGB) k_cg_update_xr(i64 n, X *x, X *r, const X
         }
         return;
     }
-    const double alpha = rho / pq;
-    const X a = (X)alpha;
+    const X a = (X)(rho / pq);
     double acc = 0;
-    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x) {
-        st_stream<X, NT>(x + i, ld_stream<X, NT>(x + i) + a * p[i]);
-        X ri = r[i] - a * ld_stream<X, NT>(q + i);
-        r[i] = ri;
-        acc += (double)ri * (double)ri;
+    while (base < hi) {
+#pragma unroll
+        for (int u = 0; u < VU; u++) {
+            const i64 i = base + (i64)u * blockDim.x;
+            if (i < hi) {
+                st_stream<X, NT>(x + i, xv[u] + a * pv[u]);
+                const X ri = rv[u] - a * qv[u];
+                r[i] = ri;
+                acc += (double)ri * (double)ri;
+            }
+        }
+        base += (i64)VU * blockDim.x;
+        load();
     }
     acc = block_sum(acc, lds);
     if (threadIdx.x == 0) {
@@ -110,24 +141,48 @@ __global__ void __launch_bounds__(CGB) k_cg_update_xr(i64 n, X *x, X *r, const X
 template <class X, bool NT>
 __global__ void __launch_bounds__(CGB) k_cg_update_p(i64 n, const X *r, X *p, const double *part_rr, CgState *st) {
     __shared__ double lds[CGB / WAVE];
-    if (wg_done(&st->done)) return;
-    const double rho1 = reduce_partials(part_rr, lds);
+    const i64 hi = slice_hi(n);
+    i64 base = slice_lo(n) + threadIdx.x;
+    X rv[VU], pv[VU];
+    auto load = [&]() {
+#pragma unroll
+        for (int u = 0; u < VU; u++) {
+            const i64 i = base + (i64)u * blockDim.x;
+            if (i < hi) {
+                rv[u] = ld_stream<X, NT>(r + i);
+                pv[u] = p[i];
+            }
+        }
+    };
+    load();
     const long long k = st->iters;
-    const double rho = st->rho[(k - 1) & 1];
+    const double rho_even = st->rho[0], rho_odd = st->rho[1];
+    const double tol = st->tol, nr0 = st->nr0;
+    const long long maxit = st->maxit;
+    double rho1;
+    if (wg_done_sum(&st->done, part_rr, CGG, lds, &rho1)) return;
+    const double rho = ((k - 1) & 1) ? rho_odd : rho_even;
     const double nr = sqrt(rho1);
     int done = 0;
     if (!isfinite(rho1)) done = 3;
-    else if (nr <= st->tol * st->nr0) done = 1;
-    else if (k >= st->maxit) done = 2;
+    else if (nr <= tol * nr0) done = 1;
+    else if (k >= maxit) done = 2;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->relres = st->nr0 > 0 ? nr / st->nr0 : 0.0;
+        st->relres = nr0 > 0 ? nr / nr0 : 0.0;
         st->rho[k & 1] = rho1;
         if (done) st->done = done;
     }
     if (done) return;
     const X beta = (X)(rho1 / rho);
-    for (i64 i = slice_lo(n) + threadIdx.x, iend = slice_hi(n); i < iend; i += blockDim.x)
-        p[i] = ld_stream<X, NT>(r + i) + beta * p[i];
+    while (base < hi) {
+#pragma unroll
+        for (int u = 0; u < VU; u++) {
+            const i64 i = base + (i64)u * blockDim.x;
+            if (i < hi) p[i] = rv[u] + beta * pv[u];
+        }
+        base += (i64)VU * blockDim.x;
+        load();
+    }
 }
 
 // ---------------------------------------------------------------- IR helpers
@@ -555,6 +610,32 @@ static void enqueue_iteration(dsm_matrix m, X *x, X *r, X *p, X *q, double *part
     constexpr bool NT = std::is_same<X, double>::value;
     hipLaunchKernelGGL((k_cg_update_xr<X, NT>), dim3(CGG), dim3(CGB), 0, s, n, x, r, p, q, part_a, npq, part_b, st);
     hipLaunchKernelGGL((k_cg_update_p<X, NT>), dim3(CGG), dim3(CGB), 0, s, n, r, p, part_b, st);
+}
+
+// Copies the state into slot (seq & 1) of a two-slot host buffer, where seq
+// counts the copies since the last k_state_seq_reset, and stores seq in the
+// copy's pad field.  The host buffer is coherent pinned memory, so the
+// stores go to host memory directly.
+__global__ void k_state_out(CgState *st, CgState *host) {
+    if (threadIdx.x != 0) return;
+    const int seq = st->pad;
+    CgState v = *st;
+    v.pad = seq;
+    host[seq & 1] = v;
+    __threadfence_system();
+    st->pad = seq + 1;
+}
+
+__global__ void k_state_seq_reset(CgState *st) {
+    if (threadIdx.x == 0) st->pad = 0;
+}
+
+void enqueue_state_out(CgState *st, CgState *host_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_out, dim3(1), dim3(WAVE), 0, s, st, host_dev);
+}
+
+void enqueue_state_seq_reset(CgState *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_seq_reset, dim3(1), dim3(WAVE), 0, s, st);
 }
 
 bool cg_graphs_enabled() {

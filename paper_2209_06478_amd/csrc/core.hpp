@@ -85,6 +85,8 @@ struct Workspace {
     void *graph = nullptr;  // hipGraphExec_t
     std::string graph_key;
     hipStream_t stream = nullptr;
+    void *host = nullptr;         // pinned host staging (hipHostMalloc)
+    void *events[2] = {nullptr, nullptr};  // hipEvent_t, for the staging slots
 };
 
 }  // namespace dsm
@@ -105,6 +107,9 @@ namespace dsm {
 // Grows (never shrinks) a workspace; contents are not preserved.
 void *ws_get(dsm_ctx ctx, Workspace &w, size_t bytes);
 void ws_release(dsm_ctx ctx, Workspace &w);
+// Releases a workspace's graph, stream, events and pinned host staging;
+// its device memory stays.
+void ws_release_host(Workspace &w);
 
 // ---------------------------------------------------------------- scan.hip
 // Exclusive prefix sum of n int32 counts into out[0..n] (out[n] = total);

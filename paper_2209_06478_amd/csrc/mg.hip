@@ -68,10 +68,7 @@ struct dsm_mg_s {
     }
     void release() {
         for (auto &l : L) dsm::ws_release(ctx, l.spws);
-        if (gws.graph) (void)hipGraphExecDestroy((hipGraphExec_t)gws.graph);
-        if (gws.stream) (void)hipStreamDestroy(gws.stream);
-        gws.graph = nullptr;
-        gws.stream = nullptr;
+        dsm::ws_release_host(gws);
         for (auto &b : bufs) dsm::dev_free(ctx, b.first, b.second);
         bufs.clear();
     }
