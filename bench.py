@@ -26,12 +26,14 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # profiles/hdc_spmv_hpcg104.md.
 # An entry is removed when its kernel changes.
 PROFILED_TRAFFIC = {
-    ("hpcg27_104", "dia", 4): 261164599,
-    ("hpcg27_104", "dia", 8): 266839979,
-    ("hpcg27_104", "dia", 10): 266196775,
-    ("hpcg27_104", "dia", 0): 262260746,
-    ("hpcg27_104", "hdc", 10): 266213878,
-    ("hpcg27_104", "hdc", 8): 266878854,
+    ("hpcg27_104", "dia", 2): 263592584,
+    ("hpcg27_104", "dia", 8): 263603118,
+    ("hpcg27_104", "dia", 10): 267859084,
+    ("hpcg27_104", "dia", 0): 262320977,
+    ("hpcg27_104", "dia", 4): 266932543,
+    ("hpcg27_104", "hdc", 2): 263491820,
+    ("hpcg27_104", "hdc", 8): 263550084,
+    ("hpcg27_104", "hdc", 10): 267940470,
 }
 
 

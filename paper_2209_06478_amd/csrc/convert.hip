@@ -621,7 +621,11 @@ static void dia_from_csr(dsm_matrix m, const Payload &C, Payload &P, const i32 *
     P.pitch = pitch_for(n);
     if (!hdc) check_pad((double)nd * (double)n, (double)C.csr_nnz, o.max_pad_ratio, "DIA");
     P.ndiag = nd;
-    P.offs = (i32 *)P.alloc(ctx, sizeof(i32) * (size_t)std::max<i64>(nd, 1));
+    // offsets padded with zeros to a multiple of 16 entries: the sweep reads
+    // them in batches of up to 16 without a bound check
+    const i64 offs_len = (std::max<i64>(nd, 1) + 15) / 16 * 16;
+    P.offs = (i32 *)P.alloc(ctx, sizeof(i32) * (size_t)offs_len);
+    DSM_HIP(hipMemsetAsync(P.offs, 0, sizeof(i32) * (size_t)offs_len, s));
     P.dval = P.alloc(ctx, sizeof(W) * (size_t)std::max<i64>(nd * P.pitch, 1));
     DSM_HIP(hipMemsetAsync(P.dval, 0, sizeof(W) * (size_t)(nd * P.pitch), s));
     hipLaunchKernelGGL(k_offsets_compact, dim3(grid_for(span, CB)), dim3(CB), 0, s, span, n, use_flag,

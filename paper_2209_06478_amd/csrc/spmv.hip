@@ -29,6 +29,7 @@ constexpr int RB_T = 1024;    // must match the row-block builder
 constexpr int CU = 4;         // CSR: entries a lane loads before gathering x
 constexpr int COO_E = 4;      // entries per lane in the COO kernel
 constexpr int COO_TE = WAVE * COO_E;
+constexpr int DIA_LOADS = 8;  // value loads a DIA lane issues per batch (16 measured no faster)
 
 template <class X>
 __device__ __forceinline__ void store_y(X *y, i64 i, X v, bool acc) {
@@ -179,6 +180,37 @@ __device__ __forceinline__ void dot_epilogue(const X (&s)[R][RW], const X *__res
     }
 }
 
+// Sixteen zero bytes in device memory: the operand address of a product
+// that must vanish (a slot past the last diagonal, a column outside the
+// matrix).  Loading from here instead of selecting the loaded value keeps
+// every load unconditional: the compiler turns a select whose operand is a
+// load into a branch around that load, which serialises the loop.
+__device__ __align__(16) unsigned char g_zero16[16];
+
+template <class T>
+__device__ __forceinline__ const T *zero_ptr() {
+    static_assert(sizeof(T) <= 16, "zero word too small");
+    return reinterpret_cast<const T *>(g_zero16);
+}
+
+// Sixteen 0xff bytes: int32 column sentinels (-1) for ELL slots past K.
+__device__ __align__(16) unsigned char g_sentinel16[16] = {0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff,
+                                                          0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff};
+
+template <class T>
+__device__ __forceinline__ const T *sentinel_ptr() {
+    static_assert(sizeof(T) <= 16, "sentinel word too small");
+    return reinterpret_cast<const T *>(g_sentinel16);
+}
+
+// Diagonals (ELL: slots) per batch of the DIA and ELL sweeps: every load of
+// a batch (values and x, for all row groups) is issued before its products
+// are summed, so a lane has 2 * KU * R * RW loads in flight.
+template <int R, int RW>
+constexpr int dia_batch() {
+    return (R * RW) >= DIA_LOADS ? 1 : DIA_LOADS / (R * RW);
+}
+
 template <class V, class X, bool ACC, bool XCD, int R, bool P2, bool DOT = false>
 __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, const i32 *__restrict__ offs,
                                             const V *__restrict__ dval, i64 pitch, const X *__restrict__ x,
@@ -186,6 +218,7 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
                                             double *__restrict__ part = nullptr, long long *count = nullptr) {
     if (stop && *stop) return;
     constexpr int RW = P2 ? 2 : 1;
+    constexpr int KU = dia_batch<R, RW>();
     const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
     const i64 i0 = (i64)b * SB * R * RW + (i64)threadIdx.x * RW;
     X s[R][RW];
@@ -193,34 +226,47 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
     for (int r = 0; r < R; r++)
 #pragma unroll
         for (int w = 0; w < RW; w++) s[r][w] = 0;
-    // Every load is unconditional at an in-range address (slot 0 / x[0]
-    // stand in for rows past the end and for columns outside the matrix; a
-    // matrix with a diagonal has ncols > 0) and the out-of-range products are
-    // selected away, so no load waits behind a branch.
-    for (i64 k = 0; k < ndiag; k++) {
-        const i64 off = offs[k];
-        const V *dk = dval + k * pitch;
+    // A slot whose column lies outside the matrix is padding (+0), and its x
+    // operand is the zero word, so its product is +0 exactly as if it were
+    // skipped; slots past the last diagonal and rows past the end read the
+    // zero word for both operands (rows past the end are never stored).
+    for (i64 k0 = 0; k0 < ndiag; k0 += KU) {
+        V v[KU][R][RW];
+        X xv[KU][R][RW];
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-            const i64 i = i0 + (i64)r * SB * RW;
-            const i64 j = i + off;
-            const bool in = i < nrows;
-            if constexpr (P2) {
-                // i is even and the pitch a multiple of 64, so the pair is
-                // aligned; slot i + 1 < pitch always exists (padding is 0)
-                const pair2<V> v = *(const pair2<V> *)(dk + (in ? i : 0));
-                const bool ok0 = in && j >= 0 && j < ncols;
-                const bool ok1 = i + 1 < nrows && j + 1 >= 0 && j + 1 < ncols;
-                const X x0 = x[ok0 ? j : 0], x1 = x[ok1 ? j + 1 : 0];
-                s[r][0] += ok0 ? widen<X>(v.a) * x0 : (X)0;
-                s[r][1] += ok1 ? widen<X>(v.b) * x1 : (X)0;
-            } else {
-                const bool ok = in && j >= 0 && j < ncols;
-                const V v = dk[in ? i : 0];
-                const X xv = x[ok ? j : 0];
-                s[r][0] += ok ? widen<X>(v) * xv : (X)0;
+        for (int u = 0; u < KU; u++) {
+            // offs is zero-padded to a multiple of 16 entries (KU divides 16)
+            const bool kin = k0 + u < ndiag;
+            const i64 k = k0 + u;
+            const i64 off = offs[k];
+            const V *dk = dval + (kin ? k : 0) * pitch;
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const i64 i = i0 + (i64)r * SB * RW;
+                const i64 j = i + off;
+                if constexpr (P2) {
+                    // i is even and the pitch a multiple of 64, so the pair is
+                    // aligned; slot i + 1 < pitch always exists (padding is 0)
+                    const pair2<V> pv = *(kin && i < nrows ? (const pair2<V> *)(dk + i) : zero_ptr<pair2<V>>());
+                    v[u][r][0] = pv.a;
+                    v[u][r][1] = pv.b;
+                    const bool ok0 = kin && i < nrows && j >= 0 && j < ncols;
+                    const bool ok1 = kin && i + 1 < nrows && j + 1 >= 0 && j + 1 < ncols;
+                    xv[u][r][0] = *(ok0 ? x + j : zero_ptr<X>());
+                    xv[u][r][1] = *(ok1 ? x + j + 1 : zero_ptr<X>());
+                } else {
+                    const bool ok = kin && i < nrows && j >= 0 && j < ncols;
+                    v[u][r][0] = *(kin && i < nrows ? dk + i : zero_ptr<V>());
+                    xv[u][r][0] = *(ok ? x + j : zero_ptr<X>());
+                }
             }
         }
+#pragma unroll
+        for (int u = 0; u < KU; u++)
+#pragma unroll
+            for (int r = 0; r < R; r++)
+#pragma unroll
+                for (int w = 0; w < RW; w++) s[r][w] += widen<X>(v[u][r][w]) * xv[u][r][w];
     }
 #pragma unroll
     for (int r = 0; r < R; r++)
@@ -239,6 +285,7 @@ __global__ void __launch_bounds__(SB) k_ell(i64 nrows, i64 K, i64 pitch, const i
                                             long long *count = nullptr) {
     if (stop && *stop) return;
     constexpr int RW = P2 ? 2 : 1;
+    constexpr int KU = dia_batch<R, RW>();
     const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
     const i64 i0 = (i64)b * SB * R * RW + (i64)threadIdx.x * RW;
     X s[R][RW];
@@ -246,38 +293,51 @@ __global__ void __launch_bounds__(SB) k_ell(i64 nrows, i64 K, i64 pitch, const i
     for (int r = 0; r < R; r++)
 #pragma unroll
         for (int w = 0; w < RW; w++) s[r][w] = 0;
-    // As in the DIA sweep: unconditional loads at in-range addresses
-    // (x[0] for padding slots: a matrix with K > 0 has ncols > 0), products
-    // of padding selected away.
-    for (i64 k = 0; k < K; k++) {
+    // Batches of KU slots: all column and value loads of a batch, then all
+    // x gathers, then the products.  Padding slots (column -1, value +0)
+    // take their x operand from the zero word, so their product is +0
+    // exactly as if skipped; slots past K and rows past the end read the
+    // sentinel column and the zero value (rows past the end are never
+    // stored).  A pair load at the last (even) row also reads the padding
+    // row after it, which exists below the pitch.
+    for (i64 k0 = 0; k0 < K; k0 += KU) {
+        i32 c[KU][R][RW];
+        V v[KU][R][RW];
+        X xv[KU][R][RW];
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-            const i64 i = i0 + (i64)r * SB * RW;
-            if constexpr (P2) {
-                // rows i (even) and i + 1; slots of rows past nrows are never
-                // read (the pair load needs both rows, a last odd row is read
-                // alone)
-                if (i + 1 < nrows) {
-                    const pair2<i32> c = *(const pair2<i32> *)(ecol + k * pitch + i);
-                    const pair2<V> v = *(const pair2<V> *)(evl + k * pitch + i);
-                    const X x0 = x[c.a >= 0 ? c.a : 0], x1 = x[c.b >= 0 ? c.b : 0];
-                    s[r][0] += c.a >= 0 ? widen<X>(v.a) * x0 : (X)0;
-                    s[r][1] += c.b >= 0 ? widen<X>(v.b) * x1 : (X)0;
-                } else if (i < nrows) {
-                    const i32 c = ecol[k * pitch + i];
-                    const V v = evl[k * pitch + i];
-                    const X xv = x[c >= 0 ? c : 0];
-                    s[r][0] += c >= 0 ? widen<X>(v) * xv : (X)0;
+        for (int u = 0; u < KU; u++)
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const i64 i = i0 + (i64)r * SB * RW;
+                const bool live = k0 + u < K && i < nrows;
+                const i64 slot = (k0 + u) * pitch + i;
+                if constexpr (P2) {
+                    const pair2<i32> cc = *(live ? (const pair2<i32> *)(ecol + slot) : sentinel_ptr<pair2<i32>>());
+                    const pair2<V> vv = *(live ? (const pair2<V> *)(evl + slot) : zero_ptr<pair2<V>>());
+                    c[u][r][0] = cc.a;
+                    c[u][r][1] = cc.b;
+                    v[u][r][0] = vv.a;
+                    v[u][r][1] = vv.b;
+                } else {
+                    c[u][r][0] = *(live ? ecol + slot : sentinel_ptr<i32>());
+                    v[u][r][0] = *(live ? evl + slot : zero_ptr<V>());
                 }
-            } else {
-                const i64 ii = i < nrows ? i : 0;
-                const i32 c0 = ecol[k * pitch + ii];
-                const i32 c = i < nrows ? c0 : -1;
-                const V v = evl[k * pitch + ii];
-                const X xv = x[c >= 0 ? c : 0];
-                s[r][0] += c >= 0 ? widen<X>(v) * xv : (X)0;
             }
-        }
+#pragma unroll
+        for (int u = 0; u < KU; u++)
+#pragma unroll
+            for (int r = 0; r < R; r++)
+#pragma unroll
+                for (int w = 0; w < RW; w++) {
+                    const i32 cc = c[u][r][w];
+                    xv[u][r][w] = *(cc >= 0 ? x + cc : zero_ptr<X>());
+                }
+#pragma unroll
+        for (int u = 0; u < KU; u++)
+#pragma unroll
+            for (int r = 0; r < R; r++)
+#pragma unroll
+                for (int w = 0; w < RW; w++) s[r][w] += widen<X>(v[u][r][w]) * xv[u][r][w];
     }
 #pragma unroll
     for (int r = 0; r < R; r++)
