@@ -55,6 +55,13 @@ struct BRes {
     int pad;
 };
 
+// y = A x by one workgroup.  Every lane issues a batch of index/value loads
+// (WB entries or diagonals) before the dependent x loads, and padding
+// entries take their x operand from the zero word (+0 products, which leave
+// the sums unchanged), so no load waits behind a branch.  Sums run in the
+// same entry / diagonal order as one entry at a time.
+constexpr int WB = 8;
+
 __device__ __forceinline__ void wg_spmv(const BReq &R, const double *__restrict__ xin, double *__restrict__ yout) {
     const int tid = threadIdx.x;
     if (R.fmt == DSM_CSR) {
@@ -64,26 +71,57 @@ __device__ __forceinline__ void wg_spmv(const BReq &R, const double *__restrict_
         for (i64 row0 = 0; row0 < R.n; row0 += per) {
             const i64 row = row0 + tid / L;
             double s = 0;
-            if (row < R.n)
-                for (i64 e = R.rp[row] + lane; e < R.rp[row + 1]; e += L) s += R.val[e] * xin[R.col[e]];
+            if (row < R.n) {
+                const i64 e1 = R.rp[row + 1];
+                for (i64 e0 = R.rp[row] + lane; e0 < e1; e0 += (i64)WB * L) {
+                    i32 c[WB];
+                    double v[WB];
+#pragma unroll
+                    for (int u = 0; u < WB; u++) {
+                        const i64 e = e0 + (i64)u * L;
+                        c[u] = *(e < e1 ? R.col + e : sentinel_ptr<i32>());
+                        v[u] = *(e < e1 ? R.val + e : zero_ptr<double>());
+                    }
+#pragma unroll
+                    for (int u = 0; u < WB; u++) s += v[u] * *(c[u] >= 0 ? xin + c[u] : zero_ptr<double>());
+                }
+            }
             for (int off = L >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, WAVE);
             if (row < R.n && lane == 0) yout[row] = s;
         }
     } else if (R.fmt == DSM_DIA) {
+        // the offsets are zero-padded to a multiple of 16 entries
         for (i64 i = tid; i < R.n; i += BB) {
             double s = 0;
-            for (i64 k = 0; k < R.ndiag; k++) {
-                const i64 j = i + R.offs[k];
-                if (j >= 0 && j < R.n) s += R.dval[k * R.pitch + i] * xin[j];
+            for (i64 k0 = 0; k0 < R.ndiag; k0 += WB) {
+                double v[WB], xv[WB];
+#pragma unroll
+                for (int u = 0; u < WB; u++) {
+                    const i64 k = k0 + u;
+                    const i64 j = i + R.offs[k];
+                    const bool kin = k < R.ndiag;
+                    v[u] = *(kin ? R.dval + k * R.pitch + i : zero_ptr<double>());
+                    xv[u] = *(kin && j >= 0 && j < R.n ? xin + j : zero_ptr<double>());
+                }
+#pragma unroll
+                for (int u = 0; u < WB; u++) s += v[u] * xv[u];
             }
             yout[i] = s;
         }
     } else {  // ELL
         for (i64 i = tid; i < R.n; i += BB) {
             double s = 0;
-            for (i64 k = 0; k < R.K; k++) {
-                const i32 c = R.ecol[k * R.pitch + i];
-                if (c >= 0) s += R.evl[k * R.pitch + i] * xin[c];
+            for (i64 k0 = 0; k0 < R.K; k0 += WB) {
+                i32 c[WB];
+                double v[WB];
+#pragma unroll
+                for (int u = 0; u < WB; u++) {
+                    const i64 k = k0 + u;
+                    c[u] = *(k < R.K ? R.ecol + k * R.pitch + i : sentinel_ptr<i32>());
+                    v[u] = *(k < R.K ? R.evl + k * R.pitch + i : zero_ptr<double>());
+                }
+#pragma unroll
+                for (int u = 0; u < WB; u++) s += v[u] * *(c[u] >= 0 ? xin + c[u] : zero_ptr<double>());
             }
             yout[i] = s;
         }

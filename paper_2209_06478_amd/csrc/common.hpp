@@ -152,6 +152,32 @@ __device__ __forceinline__ u32 xcd_tile(u32 b, u32 nblocks) {
     return base + local;
 }
 
+// ---------------------------------------------------------------- operand words
+// Sixteen zero bytes in device memory (one copy per translation unit): the
+// operand address of a product that must vanish (a slot past the last
+// diagonal, a column outside the matrix, an entry past the end of a row).
+// Loading from here instead of selecting the loaded value keeps every load
+// unconditional: the compiler turns a select whose operand is a load into a
+// branch around that load, which leaves one load in flight at a time.
+static __device__ __align__(16) unsigned char g_zero16[16];
+
+template <class T>
+__device__ __forceinline__ const T *zero_ptr() {
+    static_assert(sizeof(T) <= 16, "zero word too small");
+    return reinterpret_cast<const T *>(g_zero16);
+}
+
+// Sixteen 0xff bytes: int32 column sentinels (-1) for index slots past
+// the end.
+static __device__ __align__(16) unsigned char g_sentinel16[16] = {
+    0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff};
+
+template <class T>
+__device__ __forceinline__ const T *sentinel_ptr() {
+    static_assert(sizeof(T) <= 16, "sentinel word too small");
+    return reinterpret_cast<const T *>(g_sentinel16);
+}
+
 // ---------------------------------------------------------------- reductions
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {

@@ -99,19 +99,22 @@ __global__ void __launch_bounds__(MB) k_symgs_csr(i64 cnt, const i32 *__restrict
         i = rows[g];
         const i64 e1 = rp[i + 1];
         for (i64 base = rp[i] + lane; base < e1; base += (i64)U * W) {
+            // entries past the row and the diagonal entry take their x
+            // operand from the zero word (the diagonal is finite, so its
+            // product is a zero that leaves s unchanged): with selects on
+            // loaded values the compiler branched around each load
             i32 c[U];
-            double v[U];
+            double v[U], xv[U];
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const i64 k = base + (i64)u * W;
-                c[u] = k < e1 ? col[k] : (i32)i;
-                v[u] = k < e1 ? val[k] : 0.0;
+                c[u] = *(k < e1 ? col + k : sentinel_ptr<i32>());
+                v[u] = *(k < e1 ? val + k : zero_ptr<double>());
             }
 #pragma unroll
-            for (int u = 0; u < U; u++) {
-                const double xv = x[c[u]];  // c[u] is in range (i for padding)
-                s += c[u] != i ? v[u] * xv : 0.0;
-            }
+            for (int u = 0; u < U; u++) xv[u] = *(c[u] >= 0 && c[u] != i ? x + c[u] : zero_ptr<double>());
+#pragma unroll
+            for (int u = 0; u < U; u++) s += v[u] * xv[u];
         }
     }
     s = group_sum<W>(s);
@@ -231,8 +234,8 @@ __global__ void __launch_bounds__(SBT) k_symgs_csr_block(int nc, const i64 *__re
                 const i64 e1 = rp[i + 1];
                 for (i64 k = rp[i] + lane; k < e1; k += W) {
                     const i32 cc = col[k];
-                    const double v = val[k], xv = x[cc];
-                    s += cc != i ? v * xv : 0.0;
+                    const double v = val[k], xv = *(cc != i ? x + cc : zero_ptr<double>());
+                    s += v * xv;
                 }
             }
             s = group_sum<W>(s);

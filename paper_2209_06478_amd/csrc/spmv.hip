@@ -60,17 +60,17 @@ __global__ void __launch_bounds__(SB) k_csr_adaptive(const i32 *__restrict__ blo
         for (i64 base = e0 + tid; base < e1; base += (i64)CU * SB) {
             i32 c[CU];
             V v[CU];
+            X xv[CU];
 #pragma unroll
             for (int u = 0; u < CU; u++) {
                 const i64 e = base + (i64)u * SB;
-                if (e < e1) {
-                    c[u] = col[e];
-                    v[u] = val[e];
-                }
+                c[u] = *(e < e1 ? col + e : sentinel_ptr<i32>());
+                v[u] = *(e < e1 ? val + e : zero_ptr<V>());
             }
 #pragma unroll
-            for (int u = 0; u < CU; u++)
-                if (base + (i64)u * SB < e1) s += widen<X>(v[u]) * x[c[u]];
+            for (int u = 0; u < CU; u++) xv[u] = *(c[u] >= 0 ? x + c[u] : zero_ptr<X>());
+#pragma unroll
+            for (int u = 0; u < CU; u++) s += widen<X>(v[u]) * xv[u];
         }
         s = block_sum(s, red);
         if (tid == 0) store_y(y, r0, s, ACC);
@@ -79,23 +79,22 @@ __global__ void __launch_bounds__(SB) k_csr_adaptive(const i32 *__restrict__ blo
     {
         // fewer than 2*RB_T entries: at most 2*RB_T/SB per lane, loaded
         // together, then gathered together
+        // (slots k >= ne get +0 products, which no row reads)
         constexpr int PU = 2 * RB_T / SB;
         const int ne = (int)(e1 - e0);
         i32 c[PU];
         V v[PU];
+        X xv[PU];
 #pragma unroll
         for (int u = 0; u < PU; u++) {
             const int k = tid + u * SB;
-            if (k < ne) {
-                c[u] = col[e0 + k];
-                v[u] = val[e0 + k];
-            }
+            c[u] = *(k < ne ? col + e0 + k : sentinel_ptr<i32>());
+            v[u] = *(k < ne ? val + e0 + k : zero_ptr<V>());
         }
 #pragma unroll
-        for (int u = 0; u < PU; u++) {
-            const int k = tid + u * SB;
-            if (k < ne) prod[k] = widen<X>(v[u]) * x[c[u]];
-        }
+        for (int u = 0; u < PU; u++) xv[u] = *(c[u] >= 0 ? x + c[u] : zero_ptr<X>());
+#pragma unroll
+        for (int u = 0; u < PU; u++) prod[tid + u * SB] = widen<X>(v[u]) * xv[u];
     }
     __syncthreads();
     const int nr = (int)(r1 - r0);
@@ -128,17 +127,17 @@ __global__ void __launch_bounds__(SB) k_csr_vector(i64 nrows, const i32 *__restr
         for (i64 base = a + lane; base < c; base += (i64)CU * W) {
             i32 cc[CU];
             V v[CU];
+            X xv[CU];
 #pragma unroll
             for (int u = 0; u < CU; u++) {
                 const i64 e = base + (i64)u * W;
-                if (e < c) {
-                    cc[u] = col[e];
-                    v[u] = val[e];
-                }
+                cc[u] = *(e < c ? col + e : sentinel_ptr<i32>());
+                v[u] = *(e < c ? val + e : zero_ptr<V>());
             }
 #pragma unroll
-            for (int u = 0; u < CU; u++)
-                if (base + (i64)u * W < c) s += widen<X>(v[u]) * x[cc[u]];
+            for (int u = 0; u < CU; u++) xv[u] = *(cc[u] >= 0 ? x + cc[u] : zero_ptr<X>());
+#pragma unroll
+            for (int u = 0; u < CU; u++) s += widen<X>(v[u]) * xv[u];
         }
     }
     s = group_sum<W>(s);
@@ -178,29 +177,6 @@ __device__ __forceinline__ void dot_epilogue(const X (&s)[R][RW], const X *__res
         part[blockIdx.x] = acc;
         if (count && blockIdx.x == 0) *count += 1;
     }
-}
-
-// Sixteen zero bytes in device memory: the operand address of a product
-// that must vanish (a slot past the last diagonal, a column outside the
-// matrix).  Loading from here instead of selecting the loaded value keeps
-// every load unconditional: the compiler turns a select whose operand is a
-// load into a branch around that load, which serialises the loop.
-__device__ __align__(16) unsigned char g_zero16[16];
-
-template <class T>
-__device__ __forceinline__ const T *zero_ptr() {
-    static_assert(sizeof(T) <= 16, "zero word too small");
-    return reinterpret_cast<const T *>(g_zero16);
-}
-
-// Sixteen 0xff bytes: int32 column sentinels (-1) for ELL slots past K.
-__device__ __align__(16) unsigned char g_sentinel16[16] = {0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff,
-                                                          0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff, 0xff};
-
-template <class T>
-__device__ __forceinline__ const T *sentinel_ptr() {
-    static_assert(sizeof(T) <= 16, "sentinel word too small");
-    return reinterpret_cast<const T *>(g_sentinel16);
 }
 
 // Diagonals (ELL: slots) per batch of the DIA and ELL sweeps: every load of
@@ -374,18 +350,22 @@ __global__ void __launch_bounds__(SB) k_coo_tiles(i64 nnz, i64 nrows, const i32 
     const i64 base = t0 + (i64)lane * E;
     const int cnt = (int)max((i64)0, min((i64)E, t1 - base));
 
-    i32 r[E];
+    // entries past the end read the sentinel word as row and column (the
+    // row becomes SENT) and the zero word as value and x operand
+    i32 r[E], c[E];
+    V v[E];
     X p[E];
 #pragma unroll
     for (int k = 0; k < E; k++) {
-        if (k < cnt) {
-            r[k] = row[base + k];
-            p[k] = widen<X>(val[base + k]) * x[col[base + k]];
-        } else {
-            r[k] = SENT;
-            p[k] = 0;
-        }
+        const bool in = k < cnt;
+        r[k] = *(in ? row + base + k : sentinel_ptr<i32>());
+        c[k] = *(in ? col + base + k : sentinel_ptr<i32>());
+        v[k] = *(in ? val + base + k : zero_ptr<V>());
     }
+#pragma unroll
+    for (int k = 0; k < E; k++) r[k] = r[k] < 0 ? SENT : r[k];
+#pragma unroll
+    for (int k = 0; k < E; k++) p[k] = widen<X>(v[k]) * *(c[k] >= 0 ? x + c[k] : zero_ptr<X>());
     const i32 fr = cnt > 0 ? r[0] : SENT;
     const i32 lr = cnt > 0 ? r[cnt - 1] : SENT;
 
