@@ -78,23 +78,26 @@ __global__ void __launch_bounds__(SB) k_csr_adaptive(const i32 *__restrict__ blo
     }
     {
         // fewer than 2*RB_T entries: at most 2*RB_T/SB per lane, loaded
-        // together, then gathered together
-        // (slots k >= ne get +0 products, which no row reads)
+        // together, then gathered together (here the bounds stay branches:
+        // whole waves past the block's entries then skip their loads, which
+        // measured faster than loading the zero word)
         constexpr int PU = 2 * RB_T / SB;
         const int ne = (int)(e1 - e0);
         i32 c[PU];
         V v[PU];
-        X xv[PU];
 #pragma unroll
         for (int u = 0; u < PU; u++) {
             const int k = tid + u * SB;
-            c[u] = *(k < ne ? col + e0 + k : sentinel_ptr<i32>());
-            v[u] = *(k < ne ? val + e0 + k : zero_ptr<V>());
+            if (k < ne) {
+                c[u] = col[e0 + k];
+                v[u] = val[e0 + k];
+            }
         }
 #pragma unroll
-        for (int u = 0; u < PU; u++) xv[u] = *(c[u] >= 0 ? x + c[u] : zero_ptr<X>());
-#pragma unroll
-        for (int u = 0; u < PU; u++) prod[tid + u * SB] = widen<X>(v[u]) * xv[u];
+        for (int u = 0; u < PU; u++) {
+            const int k = tid + u * SB;
+            if (k < ne) prod[k] = widen<X>(v[u]) * x[c[u]];
+        }
     }
     __syncthreads();
     const int nr = (int)(r1 - r0);
