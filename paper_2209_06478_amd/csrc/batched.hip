@@ -103,8 +103,13 @@ __device__ __forceinline__ void wg_spmv(const BReq &R, const double *__restrict_
                     v[u] = *(kin ? R.dval + k * R.pitch + i : zero_ptr<double>());
                     xv[u] = *(kin && j >= 0 && j < R.n ? xin + j : zero_ptr<double>());
                 }
+                // zero slots are no entries (as in the device-wide sweep);
+                // the x operands are pinned as loaded so the select stays a
+                // register select
 #pragma unroll
-                for (int u = 0; u < WB; u++) s += v[u] * xv[u];
+                for (int u = 0; u < WB; u++) asm volatile("" : "+v"(xv[u]));
+#pragma unroll
+                for (int u = 0; u < WB; u++) s += v[u] * (v[u] != 0.0 ? xv[u] : 0.0);
             }
             yout[i] = s;
         }

@@ -209,6 +209,8 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
     // operand is the zero word, so its product is +0 exactly as if it were
     // skipped; slots past the last diagonal and rows past the end read the
     // zero word for both operands (rows past the end are never stored).
+    // Zero slots inside the column range drop their x operand after the load
+    // (a select on registers that are both loaded anyway).
     for (i64 k0 = 0; k0 < ndiag; k0 += KU) {
         V v[KU][R][RW];
         X xv[KU][R][RW];
@@ -240,12 +242,27 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
                 }
             }
         }
+        // pin every x operand as loaded: the select below then stays a
+        // register select instead of a branch around the load
 #pragma unroll
         for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int r = 0; r < R; r++)
 #pragma unroll
-                for (int w = 0; w < RW; w++) s[r][w] += widen<X>(v[u][r][w]) * xv[u][r][w];
+                for (int w = 0; w < RW; w++) asm volatile("" : "+v"(xv[u][r][w]));
+#pragma unroll
+        for (int u = 0; u < KU; u++)
+#pragma unroll
+            for (int r = 0; r < R; r++)
+#pragma unroll
+                for (int w = 0; w < RW; w++) {
+                    // a zero slot (padding or a stored zero, which DIA cannot
+                    // tell apart) is no entry: its x operand does not count,
+                    // so a non-finite x entry reaches only the rows that
+                    // store a nonzero in its column
+                    const X wv = widen<X>(v[u][r][w]);
+                    s[r][w] += wv * (wv != (X)0 ? xv[u][r][w] : (X)0);
+                }
     }
 #pragma unroll
     for (int r = 0; r < R; r++)

@@ -131,3 +131,54 @@ def test_spmv_eigenvector_pin():
         y = A.spmv(torch.from_numpy(v).to(dev)).cpu().numpy()
         assert np.max(np.abs(y - lam * v) / scale) <= 1e-14, f
     A.close()
+
+
+@pytest.mark.parametrize("name", ["hpcg5", "rect_empty", "banded20k"])
+def test_spmv_nonfinite_x_stays_in_its_rows(name):
+    """Non-finite x entries reach exactly the rows that store an entry in
+    their column: padding slots, slots past the last diagonal or ELL slot and
+    entries past a row's end must not turn into 0 * Inf = NaN elsewhere.
+    Rows that touch no non-finite column match the oracle (row-scaled 1e-14);
+    rows that do are non-finite, with the sign of an infinite result fixed by
+    the definition when the row sees only one infinity and no NaN."""
+    torch, dev = torch_dev()
+    p = problem(name)
+    x = x_for(p).copy()
+    bad = {0: np.inf, p.ncols - 1: np.nan, p.ncols // 2: -np.inf}
+    for j, v in bad.items():
+        x[j] = v
+    clean = x.copy()
+    for j in bad:
+        clean[j] = 0.0
+    yref, scale = oracle.spmv_csr_ref(p.row_ptr, p.col, p.val, clean)
+    touches = np.zeros(p.nrows, dtype=bool)
+    expect_inf = np.zeros(p.nrows)
+    for i in range(p.nrows):
+        cols = p.col[p.row_ptr[i]:p.row_ptr[i + 1]]
+        vals = p.val[p.row_ptr[i]:p.row_ptr[i + 1]]
+        hit = [(c, v) for c, v in zip(cols, vals) if c in bad]
+        touches[i] = bool(hit)
+        if len(hit) == 1 and np.isinf(bad[hit[0][0]]):
+            expect_inf[i] = np.sign(hit[0][1]) * np.sign(bad[hit[0][0]])
+    assert touches.any() and (~touches).any()
+    A = make_matrix(p)
+    xt = torch.from_numpy(x).to(dev)
+    for f in FORMATS:
+        log(f"[spmv nonfinite] {name} {f}")
+        try:
+            A.convert(f)
+        except dsm.DsmError as e:
+            if e.status == dsm.L.E_INFEASIBLE:
+                continue
+            raise
+        variants = range(8) if f == "csr" else (range(16) if f in ("dia", "ell", "hdc", "hyb") else [0])
+        for v in variants:
+            A.variant = v
+            y = A.spmv(xt).cpu().numpy()
+            ok = ~touches
+            assert np.all(np.isfinite(y[ok])), (name, f, v)
+            assert row_scaled_err(y[ok], yref[ok], scale[ok]) <= 1e-14, (name, f, v)
+            assert not np.any(np.isfinite(y[touches])), (name, f, v)
+            sel = expect_inf != 0
+            assert np.array_equal(np.sign(y[sel]), expect_inf[sel]), (name, f, v)
+    A.close()
