@@ -284,29 +284,52 @@ __global__ void __launch_bounds__(256) k_cgf_spmv(i64 n, i64 nd, const i32 *__re
     X s[R];
 #pragma unroll
     for (int t = 0; t < R; t++) s[t] = 0;
-    for (i64 k = 0; k < nd; k++) {
-        if constexpr (!ELL) {
-            const i64 off = offs[k];
-            const V *dk = vals + k * pitch;
+    // Batches of KU diagonals (ELL: slots): every value, r and p load of a
+    // batch is issued before its products; operands that must vanish come
+    // from the zero word (ELL columns past K from the sentinel word), and a
+    // DIA zero slot drops its operand after the loads, as in the SpMV sweep.
+    constexpr int KU = R >= 8 ? 1 : 8 / R;
+    for (i64 k0 = 0; k0 < nd; k0 += KU) {
+        V v[KU][R];
+        X rj[KU][R], pj[KU][R];
+#pragma unroll
+        for (int u = 0; u < KU; u++) {
+            const i64 k = k0 + u;
+            const bool kin = k < nd;
 #pragma unroll
             for (int t = 0; t < R; t++) {
                 const i64 i = i0 + (i64)t * 256;
-                const i64 j = i + off;
-                if (i < n && j >= 0 && j < n) {
-                    const V v = dk[i];
-                    s[t] += widen<X>(v) * p_next<X>(r[j], pold[j], beta, first);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int t = 0; t < R; t++) {
-                const i64 i = i0 + (i64)t * 256;
-                if (i < n) {
-                    const i32 c = ecol[k * pitch + i];
-                    if (c >= 0) s[t] += widen<X>(vals[k * pitch + i]) * p_next<X>(r[c], pold[c], beta, first);
+                const bool live = kin && i < n;
+                if constexpr (!ELL) {
+                    // offs is zero-padded to a multiple of 16 entries
+                    const i64 j = i + offs[k];
+                    const bool ok = live && j >= 0 && j < n;
+                    v[u][t] = *(live ? vals + k * pitch + i : zero_ptr<V>());
+                    rj[u][t] = *(ok ? r + j : zero_ptr<X>());
+                    pj[u][t] = *(ok ? pold + j : zero_ptr<X>());
+                } else {
+                    const i32 c = *(live ? ecol + k * pitch + i : sentinel_ptr<i32>());
+                    v[u][t] = *(live ? vals + k * pitch + i : zero_ptr<V>());
+                    rj[u][t] = *(c >= 0 ? r + c : zero_ptr<X>());
+                    pj[u][t] = *(c >= 0 ? pold + c : zero_ptr<X>());
                 }
             }
         }
+#pragma unroll
+        for (int u = 0; u < KU; u++)
+#pragma unroll
+            for (int t = 0; t < R; t++) {
+                asm volatile("" : "+v"(rj[u][t]));
+                asm volatile("" : "+v"(pj[u][t]));
+            }
+#pragma unroll
+        for (int u = 0; u < KU; u++)
+#pragma unroll
+            for (int t = 0; t < R; t++) {
+                const X wv = widen<X>(v[u][t]);
+                const X pv = p_next<X>(rj[u][t], pj[u][t], beta, first);
+                s[t] += wv * (ELL || wv != (X)0 ? pv : (X)0);
+            }
     }
     double acc = 0;
 #pragma unroll
