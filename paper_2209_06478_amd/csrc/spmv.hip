@@ -211,9 +211,39 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
     // zero word for both operands (rows past the end are never stored).
     // Zero slots inside the column range drop their x operand after the load
     // (a select on registers that are both loaded anyway).
+    //
+    // Rows this wave covers (all groups): [wlo, whi], as scalars.  A batch
+    // whose diagonals all exist and whose columns stay inside the matrix for
+    // every one of these rows (offsets ascend, so the first and last offset
+    // of the batch decide) takes the interior path: plain loads, no bounds
+    // tests or operand selects per element.  Only tiles near the first and
+    // last rows of a banded matrix take the general path.
+    const i64 wlo = (i64)b * SB * R * RW + (i64)__builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~(WAVE - 1))) * RW;
+    const i64 whi = wlo + (i64)(R - 1) * SB * RW + (i64)WAVE * RW - 1;
     for (i64 k0 = 0; k0 < ndiag; k0 += KU) {
         V v[KU][R][RW];
         X xv[KU][R][RW];
+        if (k0 + KU <= ndiag && whi < nrows && wlo + offs[k0] >= 0 && whi + offs[k0 + KU - 1] < ncols) {
+#pragma unroll
+            for (int u = 0; u < KU; u++) {
+                const i64 off = offs[k0 + u];
+                const V *dk = dval + (k0 + u) * pitch;
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const i64 i = i0 + (i64)r * SB * RW;
+                    if constexpr (P2) {
+                        const pair2<V> pv = *(const pair2<V> *)(dk + i);
+                        v[u][r][0] = pv.a;
+                        v[u][r][1] = pv.b;
+                        xv[u][r][0] = x[i + off];
+                        xv[u][r][1] = x[i + off + 1];
+                    } else {
+                        v[u][r][0] = dk[i];
+                        xv[u][r][0] = x[i + off];
+                    }
+                }
+            }
+        } else {
 #pragma unroll
         for (int u = 0; u < KU; u++) {
             // offs is zero-padded to a multiple of 16 entries (KU divides 16)
@@ -241,6 +271,7 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
                     xv[u][r][0] = *(ok ? x + j : zero_ptr<X>());
                 }
             }
+        }
         }
         // pin every x operand as loaded: the select below then stays a
         // register select instead of a branch around the load
