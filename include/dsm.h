@@ -221,7 +221,10 @@ dsm_status dsm_update_diagonal(dsm_matrix m, const double *d, void *stream);
 /* y = A x with x (ncols) and y (nrows) device vectors of `vec_dtype` (F64
  * or F32; they must not alias).  Products are accumulated in vec_dtype;
  * stored F32/BF16 values are widened exactly.  y is written, not read.
- * Asynchronous on `stream`. */
+ * Non-finite x entries reach only the rows that store an entry in their
+ * column: ELL/HYB padding is marked by column -1, and in DIA (and HDC's DIA
+ * part) a zero slot is no entry (padding and a stored zero are the same
+ * there, as in dsm_convert).  Asynchronous on `stream`. */
 dsm_status dsm_spmv(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, void *stream);
 
 /* y += A x, otherwise as dsm_spmv.  Lets a matrix split into parts held in
