@@ -321,8 +321,12 @@ typedef struct {
                             inner solve stops at max(inner_tol,
                             tol / (2 * current outer residual)), so the last
                             outer step reduces no further than needed         */
-    int32_t check_every; /* iterations between host checks of the device
-                            convergence flag (default: chosen by size)        */
+    int32_t check_every; /* iterations per chunk between host reads of the
+                            device solver state (default: chosen by size);
+                            the next chunk is queued before the host waits
+                            unless the residual trend predicts convergence, so
+                            at most one chunk of early-exiting kernels runs
+                            past convergence (results are unaffected)         */
     int32_t max_outer;   /* IR: outer iteration limit (default 50)             */
 } dsm_cg_opts;
 
