@@ -25,6 +25,7 @@ namespace dsm {
 
 constexpr int CB = 256;        // threads per workgroup
 constexpr int EB_ROWS = 256;   // rows per workgroup when walking entries
+constexpr int CB_U = 8;        // entries a row-per-thread kernel loads per batch
 constexpr int RB_T = 1024;     // adaptive CSR: nnz bucket per row block
 constexpr int RB_RCAP = 256;   // adaptive CSR: max rows per block
 
@@ -119,13 +120,23 @@ __global__ void k_validate_csr(i64 nrows, i64 ncols, i64 nnz, const i32 *rp, con
         atomicOr(err, 4);
         return;
     }
+    // CB_U columns loaded together (indices clamped into the row, so every
+    // load is unconditional), then checked in order
     i32 prev = -1;
-    for (i64 k = a; k < b; k++) {
-        i32 c = col[k];
-        if (c < 0 || (i64)c >= ncols) atomicOr(err, 8);
-        if (c <= prev) atomicOr(err, 16);
-        prev = c;
+    int bad = 0;
+    for (i64 k0 = a; k0 < b; k0 += CB_U) {
+        i32 c[CB_U];
+#pragma unroll
+        for (int u = 0; u < CB_U; u++) c[u] = col[min(k0 + u, b - 1)];
+#pragma unroll
+        for (int u = 0; u < CB_U; u++)
+            if (k0 + u < b) {
+                if (c[u] < 0 || (i64)c[u] >= ncols) bad |= 8;
+                if (c[u] <= prev) bad |= 16;
+                prev = c[u];
+            }
     }
+    if (bad) atomicOr(err, bad);
 }
 
 static int read_flag(int *d, hipStream_t s) {
@@ -371,13 +382,26 @@ __global__ void __launch_bounds__(CB) k_dia_scatter(i64 nrows, const i32 *rp, co
     });
 }
 
-// Per row: entries not on a true diagonal (HDC remainder).
-__global__ void k_rest_count(i64 nrows, const i32 *rp, const i32 *col, const i32 *flag, i32 *cnt) {
-    i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+// Per row: entries not on a true diagonal (HDC remainder).  Column loads of
+// CB_U entries, then their flag loads, are issued together (entries past the
+// row read the sentinel column, then the sentinel as their flag: nonzero, so
+// they count nothing).
+__global__ void __launch_bounds__(CB) k_rest_count(i64 nrows, const i32 *rp, const i32 *col, const i32 *flag,
+                                                   i32 *cnt) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nrows) return;
-    i32 c = 0;
-    for (i64 e = rp[i]; e < rp[i + 1]; e++) c += flag[(i64)col[e] - i + nrows - 1] ? 0 : 1;
-    cnt[i] = c;
+    const i64 a = rp[i], b = rp[i + 1];
+    i32 n_rest = 0;
+    for (i64 e0 = a; e0 < b; e0 += CB_U) {
+        i32 c[CB_U], f[CB_U];
+#pragma unroll
+        for (int u = 0; u < CB_U; u++) c[u] = *(e0 + u < b ? col + e0 + u : sentinel_ptr<i32>());
+#pragma unroll
+        for (int u = 0; u < CB_U; u++) f[u] = *(c[u] >= 0 ? flag + ((i64)c[u] - i + nrows - 1) : sentinel_ptr<i32>());
+#pragma unroll
+        for (int u = 0; u < CB_U; u++) n_rest += f[u] ? 0 : 1;
+    }
+    cnt[i] = n_rest;
 }
 
 template <class W>
@@ -443,20 +467,32 @@ __global__ void k_dia_merge_fill(i64 nrows, i64 ncols, i64 ndiag, const i32 *off
 }
 
 // ---------------------------------------------------------------- ELL / HYB
+// Every slot of rows [0, pitch): the k-th entry of the row for k < len, the
+// -1 column sentinel and a zero value after the row's end and in the pitch
+// padding rows (so no memset is needed first).  The loads of CB_U slots are
+// issued together; slots past the row read the sentinel and zero words, whose
+// bits are exactly the padding encoding.
 template <class W>
-__global__ void k_ell_fill(i64 nrows, const i32 *rp, const i32 *col, const W *val, i64 K, i64 pitch, i32 *ecol,
-                           W *eval) {
-    i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nrows) return;
-    i64 a = rp[i], len = rp[i + 1] - a;
-    for (i64 k = 0; k < K; k++) {
-        if (k < len) {
-            ecol[k * pitch + i] = col[a + k];
-            eval[k * pitch + i] = val[a + k];
-        } else {
-            ecol[k * pitch + i] = -1;
-            eval[k * pitch + i] = (W)0;
+__global__ void __launch_bounds__(CB) k_ell_fill(i64 nrows, i64 pitch, const i32 *rp, const i32 *col, const W *val,
+                                                 i64 K, i32 *ecol, W *eval) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= pitch) return;
+    const i64 a = i < nrows ? rp[i] : 0, len = i < nrows ? rp[i + 1] - a : 0;
+    for (i64 k0 = 0; k0 < K; k0 += CB_U) {
+        i32 c[CB_U];
+        W v[CB_U];
+#pragma unroll
+        for (int u = 0; u < CB_U; u++) {
+            const i64 k = k0 + u;
+            c[u] = *(k < len ? col + a + k : sentinel_ptr<i32>());
+            v[u] = *(k < len ? val + a + k : zero_ptr<W>());
         }
+#pragma unroll
+        for (int u = 0; u < CB_U; u++)
+            if (k0 + u < K) {
+                ecol[(k0 + u) * pitch + i] = c[u];
+                eval[(k0 + u) * pitch + i] = v[u];
+            }
     }
 }
 
@@ -688,14 +724,11 @@ static Payload from_csr_typed(dsm_matrix m, const Payload &C, int fmt, const dsm
             P.pitch = pitch_for(n);
             P.ecol = (i32 *)P.alloc(ctx, sizeof(i32) * (size_t)(K * P.pitch));
             P.evl = P.alloc(ctx, sizeof(W) * (size_t)(K * P.pitch));
-            // pitch padding rows: sentinel columns so any sweep stays valid
-            if (K > 0) {
-                DSM_HIP(hipMemsetAsync(P.ecol, 0xff, sizeof(i32) * (size_t)(K * P.pitch), s));
-                DSM_HIP(hipMemsetAsync(P.evl, 0, sizeof(W) * (size_t)(K * P.pitch), s));
-            }
-            if (n > 0 && K > 0)
-                hipLaunchKernelGGL((k_ell_fill<W>), dim3(grid_for(n, CB)), dim3(CB), 0, s, n, C.rp, C.col,
-                                   (const W *)C.val, K, P.pitch, P.ecol, (W *)P.evl);
+            // every slot, the pitch padding rows included (sentinel columns,
+            // so any sweep stays valid)
+            if (P.pitch > 0 && K > 0)
+                hipLaunchKernelGGL((k_ell_fill<W>), dim3(grid_for(P.pitch, CB)), dim3(CB), 0, s, n, P.pitch, C.rp,
+                                   C.col, (const W *)C.val, K, P.ecol, (W *)P.evl);
             DSM_HIP(hipGetLastError());
             if (fmt == DSM_HYB) {
                 Tmp cnt(ctx, sizeof(i32) * (size_t)std::max<i64>(n, 1)), orp(ctx, sizeof(i32) * (size_t)(n + 1));
