@@ -94,8 +94,9 @@ inline double next_relres(double older, double last) {
 // within the running chunk: the device then never idles between chunks,
 // and a chunk enqueued past convergence only pays its launches (every
 // kernel of the loop checks the done flag first).  With use_graph the chunk
-// is captured once per `key` into gws (replayed on gws's private stream
-// after `s` has drained); if capture fails the chunk runs eagerly on `s`.
+// is captured once per `key` into gws (replayed on gws's private stream,
+// which first waits for the work already queued on `s`); if capture fails
+// the chunk runs eagerly on `s`.
 // Returns after every enqueued chunk has finished, with the last state.
 template <class Enq>
 CgState run_chunks(Workspace &gws, const std::string &key, bool use_graph, int every, long long cap,
@@ -141,7 +142,12 @@ CgState run_chunks(Workspace &gws, const std::string &key, bool use_graph, int e
         exec = (hipGraphExec_t)gws.graph;
     }
     hipStream_t rs = exec ? gws.stream : s;
-    if (exec) DSM_HIP(hipStreamSynchronize(s));  // set-up work done before the replays
+    if (exec) {
+        // the replays wait for the set-up work on `s` on the device (an
+        // event, not a host round trip)
+        DSM_HIP(hipEventRecord((hipEvent_t)gws.events[0], s));
+        DSM_HIP(hipStreamWaitEvent(rs, (hipEvent_t)gws.events[0], 0));
+    }
     enqueue_state_seq_reset(st, rs);
 
     long long steps = 0;
