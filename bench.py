@@ -26,14 +26,20 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # profiles/hdc_spmv_hpcg104.md.
 # An entry is removed when its kernel changes.
 PROFILED_TRAFFIC = {
-    ("hpcg27_104", "dia", 8): 264403487,
-    ("hpcg27_104", "dia", 2): 265871133,
-    ("hpcg27_104", "dia", 10): 267213712,
-    ("hpcg27_104", "dia", 0): 262244923,
-    ("hpcg27_104", "dia", 4): 266901641,
-    ("hpcg27_104", "hdc", 8): 264369387,
-    ("hpcg27_104", "hdc", 2): 265712657,
-    ("hpcg27_104", "hdc", 10): 267275212,
+    ("hpcg27_104", "dia", 16): 263109254,
+    ("hpcg27_104", "dia", 2): 265907868,
+    ("hpcg27_104", "dia", 8): 264346094,
+    ("hpcg27_104", "dia", 10): 267432217,
+    ("hpcg27_104", "dia", 0): 262245969,
+    ("hpcg27_104", "dia", 4): 266914344,
+    ("hpcg27_104", "dia", 18): 270264848,
+    ("hpcg27_104", "dia", 20): 276324504,
+    ("hpcg27_104", "dia", 21): 297702406,
+    ("hpcg27_104", "hdc", 16): 263059197,
+    ("hpcg27_104", "hdc", 2): 265779875,
+    ("hpcg27_104", "hdc", 8): 264266303,
+    ("hpcg27_104", "hdc", 10): 267441451,
+    ("hpcg27_104", "hdc", 18): 270179033,
 }
 
 

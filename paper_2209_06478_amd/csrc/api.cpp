@@ -428,7 +428,8 @@ DSM_API dsm_status dsm_set_variant(dsm_matrix m, int32_t variant) {
     return guard([&] {
         check_matrix(m);
         const int f = m->P.fmt;
-        int maxv = f == DSM_CSR ? CSR_VARIANTS : (f == DSM_COO ? 1 : SWEEP_VARIANT_COUNT);
+        int maxv = f == DSM_CSR ? CSR_VARIANTS
+                   : (f == DSM_COO ? 1 : ((f == DSM_DIA || f == DSM_HDC) ? DIA_VARIANT_COUNT : SWEEP_VARIANT_COUNT));
         DSM_CHECK(variant >= 0 && variant < maxv, DSM_E_INVALID, "no such kernel variant for this format");
         m->variant = variant;
     });

@@ -666,6 +666,22 @@ static void dia_from_csr(dsm_matrix m, const Payload &C, Payload &P, const i32 *
     DSM_HIP(hipMemsetAsync(P.dval, 0, sizeof(W) * (size_t)(nd * P.pitch), s));
     hipLaunchKernelGGL(k_offsets_compact, dim3(grid_for(span, CB)), dim3(CB), 0, s, span, n, use_flag,
                        slot.as<i32>(), P.offs);
+    // diagonal clusters for the LDS-staged sweep (host pass over the offsets)
+    if (nd > 0) {
+        std::vector<i32> ho((size_t)nd), hc;
+        DSM_HIP(hipMemcpyAsync(ho.data(), P.offs, sizeof(i32) * (size_t)nd, hipMemcpyDeviceToHost, s));
+        sync(s);
+        for (i64 k = 0; k < nd;) {
+            i64 e = k + 1;
+            while (e < nd && e - k < DIA_CLUSTER_K && (i64)ho[e] - ho[k] <= DIA_CLUSTER_SPAN) e++;
+            hc.insert(hc.end(), {(i32)k, (i32)e, ho[k], ho[e - 1]});
+            k = e;
+        }
+        P.nclu = (i64)hc.size() / 4;
+        P.clu = (i32 *)P.alloc(ctx, sizeof(i32) * hc.size());
+        DSM_HIP(hipMemcpyAsync(P.clu, hc.data(), sizeof(i32) * hc.size(), hipMemcpyHostToDevice, s));
+        sync(s);  // hc is a host temporary
+    }
     if (n > 0)
         hipLaunchKernelGGL((k_dia_scatter<W>), dim3(entry_grid(n)), dim3(CB), 0, s, n, C.rp, C.col,
                            (const W *)C.val, hdc ? use_flag : (const i32 *)nullptr, slot.as<i32>(), P.pitch,

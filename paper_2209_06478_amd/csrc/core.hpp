@@ -51,6 +51,11 @@ struct Payload {
     i32 *offs = nullptr;
     void *dval = nullptr;
     i64 ndiag = 0;
+    // diagonals grouped into clusters of up to DIA_CLUSTER_K consecutive
+    // diagonals whose offsets span at most DIA_CLUSTER_SPAN: nclu entries of
+    // {first diagonal, one past the last, lowest offset, highest offset}
+    i32 *clu = nullptr;
+    i64 nclu = 0;
     // ELL (HYB)
     i32 *ecol = nullptr;
     void *evl = nullptr;
@@ -166,6 +171,10 @@ double spmv_bytes(const dsm_matrix_s *m, const Payload &P, int vec_dtype);
 // variants (tile order x row groups per thread x paired rows).
 constexpr int CSR_VARIANTS = 8;
 constexpr int SWEEP_VARIANT_COUNT = 16;
+// DIA/HDC also take bit 4: x staged in LDS per diagonal cluster.
+constexpr int DIA_VARIANT_COUNT = 32;
+constexpr int DIA_CLUSTER_K = 3;
+constexpr int DIA_CLUSTER_SPAN = 64;
 
 // ---------------------------------------------------------------- cg.hip / batched.hip
 // CG with caller-provided workspaces (vectors/scalars, SpMV scratch).

@@ -345,8 +345,8 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
                 variants = f == DSM_CSR ? std::vector<int>{1, 2, 4, 8, 16, 32} : std::vector<int>{1};
             } else if (o.tune_variant) {
                 if (f == DSM_CSR) variants = {0, 7, 2, 3, 4, 5, 6};
-                else if (f == DSM_DIA || f == DSM_ELL || f == DSM_HDC || f == DSM_HYB)
-                    variants = {0, 1, 2, 4, 8, 10, 12};
+                else if (f == DSM_DIA || f == DSM_HDC) variants = {0, 1, 2, 4, 8, 10, 12, 16, 18, 20, 19, 21};
+                else if (f == DSM_ELL || f == DSM_HYB) variants = {0, 1, 2, 4, 8, 10, 12};
             }
             double tf = 0;
             int vf = 0;

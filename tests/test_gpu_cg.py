@@ -37,6 +37,28 @@ def test_cg_hpcg16_every_format(fmt):
     assert np.linalg.norm(x - xo) <= 10 * KAPPA[16] * 1e-10 * np.linalg.norm(xo)
 
 
+@pytest.mark.parametrize("fmt,variant", [("dia", v) for v in (0, 2, 8, 13, 16, 19, 21, 31)] + [("hdc", 18), ("ell", 10)])
+def test_cg_sweep_variants(fmt, variant):
+    """The three-kernel loop with the sweep's p.q epilogue in every kind of
+    sweep (gathered x, paired rows, LDS-staged x with 1, 2 and 4 row groups,
+    both tile orders) reaches the oracle's iterate."""
+    torch, dev = torch_dev()
+    p = problem("hpcg16")
+    xo, it, rr, st = oracle.cg(p.row_ptr, p.col, p.val, p.b, tol=1e-10)
+    log(f"[cg] hpcg16 {fmt} v{variant}")
+    A = make_matrix(p)
+    A.convert(fmt)
+    A.variant = variant
+    b = torch.from_numpy(p.b).to(dev)
+    x, res = A.cg(b, tol=1e-10)
+    x = x.cpu().numpy()
+    A.close()
+    assert res["status"] == "converged"
+    assert abs(res["iters"] - it) <= 1, (res, it)
+    assert oracle.true_relres(p.row_ptr, p.col, p.val, p.b, x) <= 1.5e-10
+    assert np.linalg.norm(x - xo) <= 10 * KAPPA[16] * 1e-10 * np.linalg.norm(xo)
+
+
 def test_cg_hpcg104_dia_and_csr():
     p = problem("hpcg104")
     for fmt in ["dia", "csr"]:

@@ -32,7 +32,7 @@ def run_formats(name, formats=FORMATS, tol=1e-14):
                 out[f] = "infeasible"
                 continue
             raise
-        variants = range(8) if f == "csr" else (range(16) if f in ("dia", "ell", "hdc", "hyb") else [0])
+        variants = range(8) if f == "csr" else (range(32) if f in ("dia", "hdc") else (range(16) if f in ("ell", "hyb") else [0]))
         for v in variants:
             A.variant = v
             y = A.spmv(xt)
@@ -171,7 +171,7 @@ def test_spmv_nonfinite_x_stays_in_its_rows(name):
             if e.status == dsm.L.E_INFEASIBLE:
                 continue
             raise
-        variants = range(8) if f == "csr" else (range(16) if f in ("dia", "ell", "hdc", "hyb") else [0])
+        variants = range(8) if f == "csr" else (range(32) if f in ("dia", "hdc") else (range(16) if f in ("ell", "hyb") else [0]))
         for v in variants:
             A.variant = v
             y = A.spmv(xt).cpu().numpy()
