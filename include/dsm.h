@@ -239,7 +239,7 @@ dsm_status dsm_spmv_accumulate(dsm_matrix m, const void *x, void *y, dsm_dtype v
  * log2 of the row groups per thread (1, 2, 4, 4), bit 3 = groups of two
  * adjacent rows fetched with double-width loads.  DIA and HDC also take
  * bit 4 (16..31): x is staged in LDS once per cluster of up to 3 nearby
- * diagonals instead of gathered per diagonal (bit 3 is then ignored).
+ * diagonals instead of gathered per diagonal (bits 0-3 keep their meaning).
  * COO: 0.  Set by dsm_select or directly; an out-of-range value gives
  * DSM_E_INVALID. */
 dsm_status dsm_set_variant(dsm_matrix m, int32_t variant);

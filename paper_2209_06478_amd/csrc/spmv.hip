@@ -308,8 +308,9 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
     if constexpr (DOT) dot_epilogue<X, R, RW>(s, x, i0, nrows, part, count);
 }
 
-// DIA sweep with x staged in LDS (variant bit 4).  A workgroup owns T = SB*R
-// consecutive rows (thread t: rows r0 + t + q*SB).  For each cluster of
+// DIA sweep with x staged in LDS (variant bit 4).  A workgroup owns
+// T = SB*R*RW consecutive rows (thread t: rows r0 + t*RW + q*SB*RW (+1 with
+// paired rows, whose values come in one double-width load)).  For each cluster of
 // nearby diagonals (offsets lo..hi, at most DIA_CLUSTER_SPAN apart) it
 // loads the x window [r0 + lo, r0 + hi + T) once, coalesced, into LDS, and
 // every diagonal of the cluster reads its operands there instead of
@@ -318,35 +319,39 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
 // (their slots are padding, +0); zero slots drop their operand as in k_dia.
 // Measured faster than k_dia beyond the Infinity Cache (HPCG 128^3 and
 // 144^3), slower at 104^3, where k_dia's gathers hit the caches.
-template <class V, class X, bool ACC, bool XCD, int R, bool DOT = false>
+template <class V, class X, bool ACC, bool XCD, int R, bool P2, bool DOT = false>
 __global__ void __launch_bounds__(SB) k_dia_lds(i64 nrows, i64 ncols, i64 nclu, const i32 *__restrict__ clu,
                                                 const i32 *__restrict__ offs, const V *__restrict__ dval, i64 pitch,
                                                 const X *__restrict__ x, X *__restrict__ y,
                                                 const int *__restrict__ stop, double *__restrict__ part = nullptr,
                                                 long long *count = nullptr) {
     if (stop && *stop) return;
-    constexpr int T = SB * R;
+    constexpr int RW = P2 ? 2 : 1;
+    constexpr int T = SB * R * RW;
     constexpr int WMAX = T + DIA_CLUSTER_SPAN;
     constexpr int WP = (WMAX + SB - 1) / SB;
     constexpr int KC = DIA_CLUSTER_K;
     __shared__ X xs[WMAX];
     const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
     const i64 r0 = (i64)b * T;
-    X s[R][1];
+    const int t0 = threadIdx.x * RW;  // first row of this thread's group 0, within the tile
+    X s[R][RW];
 #pragma unroll
-    for (int q = 0; q < R; q++) s[q][0] = 0;
+    for (int q = 0; q < R; q++)
+#pragma unroll
+        for (int w = 0; w < RW; w++) s[q][w] = 0;
     for (i64 c = 0; c < nclu; c++) {
         const i64 kb = clu[4 * c], ke = clu[4 * c + 1], lo = clu[4 * c + 2], hi = clu[4 * c + 3];
         const i64 base = r0 + lo;
         const int W = T + (int)(hi - lo);
-        X w[WP];
+        X win[WP];
 #pragma unroll
         for (int p = 0; p < WP; p++) {
             const int t = threadIdx.x + p * SB;
             const i64 j = base + t;
-            w[p] = *(t < W && j >= 0 && j < ncols ? x + j : zero_ptr<X>());
+            win[p] = *(t < W && j >= 0 && j < ncols ? x + j : zero_ptr<X>());
         }
-        V v[KC][R];
+        V v[KC][R][RW];
         int d[KC];
 #pragma unroll
         for (int u = 0; u < KC; u++) {
@@ -354,33 +359,46 @@ __global__ void __launch_bounds__(SB) k_dia_lds(i64 nrows, i64 ncols, i64 nclu, 
             d[u] = kin ? offs[kb + u] - (int)lo : 0;
 #pragma unroll
             for (int q = 0; q < R; q++) {
-                const i64 i = r0 + threadIdx.x + q * SB;
-                v[u][q] = *(kin && i < nrows ? dval + (kb + u) * pitch + i : zero_ptr<V>());
+                const i64 i = r0 + t0 + (i64)q * SB * RW;
+                const V *dk = dval + (kb + u) * pitch;
+                if constexpr (P2) {
+                    // i is even and the pitch a multiple of 64: the pair is
+                    // aligned and slot i + 1 < pitch exists (padding is 0)
+                    const pair2<V> pv = *(kin && i < nrows ? (const pair2<V> *)(dk + i) : zero_ptr<pair2<V>>());
+                    v[u][q][0] = pv.a;
+                    v[u][q][1] = pv.b;
+                } else {
+                    v[u][q][0] = *(kin && i < nrows ? dk + i : zero_ptr<V>());
+                }
             }
         }
         __syncthreads();  // the previous cluster's reads of xs are done
 #pragma unroll
         for (int p = 0; p < WP; p++) {
             const int t = threadIdx.x + p * SB;
-            if (t < W) xs[t] = w[p];
+            if (t < W) xs[t] = win[p];
         }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < KC; u++)
 #pragma unroll
-            for (int q = 0; q < R; q++) {
-                X xv = xs[threadIdx.x + q * SB + d[u]];
-                asm volatile("" : "+v"(xv));
-                const X wv = widen<X>(v[u][q]);
-                s[q][0] += wv * (wv != (X)0 ? xv : (X)0);
-            }
+            for (int q = 0; q < R; q++)
+#pragma unroll
+                for (int w = 0; w < RW; w++) {
+                    X xv = xs[t0 + q * SB * RW + w + d[u]];
+                    asm volatile("" : "+v"(xv));
+                    const X wv = widen<X>(v[u][q][w]);
+                    s[q][w] += wv * (wv != (X)0 ? xv : (X)0);
+                }
     }
 #pragma unroll
-    for (int q = 0; q < R; q++) {
-        const i64 i = r0 + threadIdx.x + (i64)q * SB;
-        if (i < nrows) store_y(y, i, s[q][0], ACC);
-    }
-    if constexpr (DOT) dot_epilogue<X, R, 1>(s, x, r0 + threadIdx.x, nrows, part, count);
+    for (int q = 0; q < R; q++)
+#pragma unroll
+        for (int w = 0; w < RW; w++) {
+            const i64 i = r0 + t0 + (i64)q * SB * RW + w;
+            if (i < nrows) store_y(y, i, s[q][w], ACC);
+        }
+    if constexpr (DOT) dot_epilogue<X, R, RW>(s, x, r0 + t0, nrows, part, count);
 }
 
 template <class V, class X, bool ACC, bool XCD, int R, bool P2, bool DOT = false>
@@ -663,28 +681,25 @@ static void csr_launch(dsm_matrix m, const Payload &P, const X *x, X *y, int var
 }
 
 // Launch geometry of a sweep variant (workgroups = partials of the dot form).
-// Bit 4 (DIA/HDC only) selects the LDS-staged sweep, which has no paired
-// form: bit 3 is ignored there.
 static unsigned sweep_groups(i64 n, int variant) {
     const int lr = (variant >> 1) & 3, R = lr == 0 ? 1 : (lr == 1 ? 2 : 4);
-    const bool pairs = ((variant >> 3) & 1) && !((variant >> 4) & 1);
-    return grid_for(n, SB * R * (pairs ? 2 : 1));
+    return grid_for(n, SB * R * (((variant >> 3) & 1) ? 2 : 1));
 }
 
-template <class V, class X, bool ACC, bool XCD, int R, bool DOT>
+template <class V, class X, bool ACC, bool XCD, int R, bool P2, bool DOT>
 static void sweep_lds_launch(dsm_matrix m, const Payload &P, const X *x, X *y, hipStream_t s, const int *stop,
                              double *part, long long *count) {
     const i64 n = m->nrows;
-    hipLaunchKernelGGL((k_dia_lds<V, X, ACC, XCD, R, DOT>), dim3(grid_for(n, SB * R)), dim3(SB), 0, s, n, m->ncols,
-                       P.nclu, P.clu, P.offs, (const V *)P.dval, P.pitch, x, y, stop, part, count);
+    hipLaunchKernelGGL((k_dia_lds<V, X, ACC, XCD, R, P2, DOT>), dim3(grid_for(n, SB * R * (P2 ? 2 : 1))), dim3(SB),
+                       0, s, n, m->ncols, P.nclu, P.clu, P.offs, (const V *)P.dval, P.pitch, x, y, stop, part, count);
 }
 
-template <class V, class X, bool ACC, bool XCD, bool DOT>
+template <class V, class X, bool ACC, bool XCD, bool P2, bool DOT>
 static void sweep_lds_r(dsm_matrix m, const Payload &P, const X *x, X *y, int lr, hipStream_t s, const int *stop,
                         double *part, long long *count) {
-    if (lr == 0) sweep_lds_launch<V, X, ACC, XCD, 1, DOT>(m, P, x, y, s, stop, part, count);
-    else if (lr == 1) sweep_lds_launch<V, X, ACC, XCD, 2, DOT>(m, P, x, y, s, stop, part, count);
-    else sweep_lds_launch<V, X, ACC, XCD, 4, DOT>(m, P, x, y, s, stop, part, count);
+    if (lr == 0) sweep_lds_launch<V, X, ACC, XCD, 1, P2, DOT>(m, P, x, y, s, stop, part, count);
+    else if (lr == 1) sweep_lds_launch<V, X, ACC, XCD, 2, P2, DOT>(m, P, x, y, s, stop, part, count);
+    else sweep_lds_launch<V, X, ACC, XCD, 4, P2, DOT>(m, P, x, y, s, stop, part, count);
 }
 
 template <class V, class X, bool ACC, bool XCD, int R, bool P2, bool DOT>
@@ -714,8 +729,10 @@ static void sweep(dsm_matrix m, const Payload &P, const X *x, X *y, int variant,
     const bool xcd = !(variant & 1), p2 = (variant >> 3) & 1;
     const int lr = (variant >> 1) & 3;
     if (((variant >> 4) & 1) && (P.fmt == DSM_DIA || P.fmt == DSM_HDC)) {
-        if (xcd) sweep_lds_r<V, X, ACC, true, DOT>(m, P, x, y, lr, s, stop, part, count);
-        else sweep_lds_r<V, X, ACC, false, DOT>(m, P, x, y, lr, s, stop, part, count);
+        if (xcd && p2) sweep_lds_r<V, X, ACC, true, true, DOT>(m, P, x, y, lr, s, stop, part, count);
+        else if (xcd) sweep_lds_r<V, X, ACC, true, false, DOT>(m, P, x, y, lr, s, stop, part, count);
+        else if (p2) sweep_lds_r<V, X, ACC, false, true, DOT>(m, P, x, y, lr, s, stop, part, count);
+        else sweep_lds_r<V, X, ACC, false, false, DOT>(m, P, x, y, lr, s, stop, part, count);
         return;
     }
     if (xcd && p2) sweep_r<V, X, ACC, true, true, DOT>(m, P, x, y, lr, s, stop, part, count);
