@@ -26,20 +26,20 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # profiles/hdc_spmv_hpcg104.md.
 # An entry is removed when its kernel changes.
 PROFILED_TRAFFIC = {
-    ("hpcg27_104", "dia", 16): 263109254,
-    ("hpcg27_104", "dia", 2): 265907868,
-    ("hpcg27_104", "dia", 8): 264346094,
-    ("hpcg27_104", "dia", 10): 267432217,
-    ("hpcg27_104", "dia", 0): 262245969,
-    ("hpcg27_104", "dia", 4): 266914344,
-    ("hpcg27_104", "dia", 18): 270264848,
-    ("hpcg27_104", "dia", 20): 276324504,
-    ("hpcg27_104", "dia", 21): 297702406,
-    ("hpcg27_104", "hdc", 16): 263059197,
-    ("hpcg27_104", "hdc", 2): 265779875,
-    ("hpcg27_104", "hdc", 8): 264266303,
-    ("hpcg27_104", "hdc", 10): 267441451,
-    ("hpcg27_104", "hdc", 18): 270179033,
+    ("hpcg27_104", "dia", 16): 263025592,
+    ("hpcg27_104", "dia", 2): 265736183,
+    ("hpcg27_104", "dia", 8): 264340832,
+    ("hpcg27_104", "dia", 10): 267517561,
+    ("hpcg27_104", "dia", 0): 262239624,
+    ("hpcg27_104", "dia", 4): 266912308,
+    ("hpcg27_104", "dia", 18): 270304131,
+    ("hpcg27_104", "dia", 20): 276654995,
+    ("hpcg27_104", "dia", 21): 297393076,
+    ("hpcg27_104", "hdc", 16): 262987028,
+    ("hpcg27_104", "hdc", 2): 265620509,
+    ("hpcg27_104", "hdc", 8): 264259060,
+    ("hpcg27_104", "hdc", 10): 267533438,
+    ("hpcg27_104", "hdc", 18): 270161215,
 }
 
 
