@@ -345,14 +345,40 @@ __global__ void __launch_bounds__(SB) k_dia_lds(i64 nrows, i64 ncols, i64 nclu, 
         const i64 base = r0 + lo;
         const int W = T + (int)(hi - lo);
         X win[WP];
+        V v[KC][R][RW];
+        int d[KC];
+        // FP32/BF16 values: a cluster with all KC diagonals, rows all inside
+        // the matrix and a window inside x takes plain loads (the index work
+        // per element limits those sweeps, as in k_dia)
+        if (sizeof(V) < sizeof(double) && ke - kb == KC && r0 + T <= nrows && base >= 0 && base + W <= ncols) {
+#pragma unroll
+            for (int p = 0; p < WP; p++) {
+                const int t = threadIdx.x + p * SB;
+                win[p] = x[base + min(t, W - 1)];
+            }
+#pragma unroll
+            for (int u = 0; u < KC; u++) {
+                d[u] = offs[kb + u] - (int)lo;
+                const V *dk = dval + (kb + u) * pitch;
+#pragma unroll
+                for (int q = 0; q < R; q++) {
+                    const i64 i = r0 + t0 + (i64)q * SB * RW;
+                    if constexpr (P2) {
+                        const pair2<V> pv = *(const pair2<V> *)(dk + i);
+                        v[u][q][0] = pv.a;
+                        v[u][q][1] = pv.b;
+                    } else {
+                        v[u][q][0] = dk[i];
+                    }
+                }
+            }
+        } else {
 #pragma unroll
         for (int p = 0; p < WP; p++) {
             const int t = threadIdx.x + p * SB;
             const i64 j = base + t;
             win[p] = *(t < W && j >= 0 && j < ncols ? x + j : zero_ptr<X>());
         }
-        V v[KC][R][RW];
-        int d[KC];
 #pragma unroll
         for (int u = 0; u < KC; u++) {
             const bool kin = kb + u < ke;
@@ -371,6 +397,7 @@ __global__ void __launch_bounds__(SB) k_dia_lds(i64 nrows, i64 ncols, i64 nclu, 
                     v[u][q][0] = *(kin && i < nrows ? dk + i : zero_ptr<V>());
                 }
             }
+        }
         }
         __syncthreads();  // the previous cluster's reads of xs are done
 #pragma unroll
