@@ -187,8 +187,13 @@ __global__ void __launch_bounds__(SBT) k_symgs_dia_block(int nc, const i64 *__re
                                                          const i32 *__restrict__ offs,
                                                          const double *__restrict__ dperm, i64 pitch,
                                                          const double *__restrict__ diag,
-                                                         const double *__restrict__ r, double *x, const int *stop) {
+                                                         const double *__restrict__ r, double *x, const int *stop,
+                                                         int from_zero) {
     if (stopped(stop)) return;
+    if (from_zero) {
+        for (i64 i = threadIdx.x; i < n; i += SBT) x[i] = 0.0;
+        __syncthreads();
+    }
     for (int step = 0; step < 2 * nc - 1; step++) {
         const int c = sweep_colour(step, nc);
         const i64 t1 = cstart[c + 1];
@@ -216,8 +221,13 @@ __global__ void __launch_bounds__(SBT) k_symgs_csr_block(int nc, const i64 *__re
                                                          const i32 *__restrict__ col,
                                                          const double *__restrict__ val,
                                                          const double *__restrict__ diag,
-                                                         const double *__restrict__ r, double *x, const int *stop) {
+                                                         const double *__restrict__ r, double *x, const int *stop,
+                                                         i64 n, int from_zero) {
     if (stopped(stop)) return;
+    if (from_zero) {
+        for (i64 i = threadIdx.x; i < n; i += SBT) x[i] = 0.0;
+        __syncthreads();
+    }
     const int lane = threadIdx.x % W, grp = threadIdx.x / W;
     constexpr int G = SBT / W;
     for (int step = 0; step < 2 * nc - 1; step++) {
@@ -243,6 +253,22 @@ __global__ void __launch_bounds__(SBT) k_symgs_csr_block(int nc, const i64 *__re
         }
         __syncthreads();
     }
+}
+
+// The first colour of a sweep that starts from x = 0, for every level row at
+// once: rows of colour 0 see only zero neighbours, so their update is
+// r_i / a_ii exactly as the sweep computes it ((r_i - (+0)) / a_ii); every
+// other row starts at 0.  Replaces the zeroing launch and the first colour
+// launch.  t walks the colour-ordered rows, colour 0 being [0, n0).
+__global__ void k_symgs_first_from_zero(i64 n, i64 n0, const i32 *__restrict__ rows,
+                                        const double *__restrict__ diag, const double *__restrict__ r,
+                                        double *__restrict__ x, const int *stop) {
+    const bool halt = stopped(stop);
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const i64 i = rows[t];
+    const double v = t < n0 ? (r[i] - 0.0) / diag[i] : 0.0;
+    if (!halt) x[i] = v;
 }
 
 __global__ void k_mg_zero(i64 n, double *x, const int *stop) {
@@ -480,7 +506,10 @@ static void check_level_format(const dsm_mg_s::Level &l) {
 }
 
 // One symmetric Gauss-Seidel sweep on level l: x <- S(x) for A_l x = r.
-static void symgs(dsm_mg_s *mg, int l, const double *r, double *x, hipStream_t s, const int *stop) {
+// One symmetric sweep on level l.  from_zero: x is first set to zero (the
+// pre-smoothing of a V-cycle), folded into the sweep's first launch.
+static void symgs(dsm_mg_s *mg, int l, const double *r, double *x, hipStream_t s, const int *stop,
+                  bool from_zero = false) {
     auto &lv = mg->L[l];
     const Payload &P = lv.A->P;
     const int nc = (int)lv.cstart.size() - 1;
@@ -488,10 +517,10 @@ static void symgs(dsm_mg_s *mg, int l, const double *r, double *x, hipStream_t s
     if (lv.n <= BLOCK_LEVEL_ROWS) {
         if (lv.fmt == DSM_CSR)
             hipLaunchKernelGGL(k_symgs_csr_block<GSW>, dim3(1), dim3(SBT), 0, s, nc, lv.cstart_d, lv.rows, P.rp,
-                               P.col, (const double *)P.val, lv.diag, r, x, stop);
+                               P.col, (const double *)P.val, lv.diag, r, x, stop, lv.n, (int)from_zero);
         else
             hipLaunchKernelGGL(k_symgs_dia_block, dim3(1), dim3(SBT), 0, s, nc, lv.cstart_d, lv.rows, lv.n, P.ndiag,
-                               P.offs, lv.dperm, P.pitch, lv.diag, r, x, stop);
+                               P.offs, lv.dperm, P.pitch, lv.diag, r, x, stop, (int)from_zero);
         DSM_HIP(hipGetLastError());
         return;
     }
@@ -505,7 +534,13 @@ static void symgs(dsm_mg_s *mg, int l, const double *r, double *x, hipStream_t s
             hipLaunchKernelGGL(k_symgs_dia<GSR>, dim3(grid_for(cnt, MB * GSR)), dim3(MB), 0, s, c0, cnt, lv.rows,
                                lv.n, P.ndiag, P.offs, lv.dperm, P.pitch, lv.diag, r, x, stop);
     };
-    for (int c = 0; c < nc; c++) colour(c);
+    int c_first = 0;
+    if (from_zero) {
+        hipLaunchKernelGGL(k_symgs_first_from_zero, dim3(grid_for(lv.n, MB)), dim3(MB), 0, s, lv.n, lv.cstart[1],
+                           lv.rows, lv.diag, r, x, stop);
+        c_first = 1;
+    }
+    for (int c = c_first; c < nc; c++) colour(c);
     for (int c = nc - 2; c >= 0; c--) colour(c);
     DSM_HIP(hipGetLastError());
 }
@@ -513,8 +548,8 @@ static void symgs(dsm_mg_s *mg, int l, const double *r, double *x, hipStream_t s
 // x = M r on level l (x is overwritten; one V-cycle from zero)
 static void vcycle(dsm_mg_s *mg, int l, const double *r, double *x, hipStream_t s, const int *stop) {
     auto &lv = mg->L[l];
-    hipLaunchKernelGGL(k_mg_zero, dim3(grid_for(lv.n, MB)), dim3(MB), 0, s, lv.n, x, stop);
-    symgs(mg, l, r, x, s, stop);
+    if (lv.cstart.size() > 1) symgs(mg, l, r, x, s, stop, true);
+    else hipLaunchKernelGGL(k_mg_zero, dim3(grid_for(lv.n, MB)), dim3(MB), 0, s, lv.n, x, stop);
     if (l + 1 == (int)mg->L.size()) return;
     auto &cv = mg->L[l + 1];
     const Payload &P = lv.A->P;
