@@ -40,6 +40,16 @@ PROFILED_TRAFFIC = {
     ("hpcg27_104", "hdc", 8): 264259060,
     ("hpcg27_104", "hdc", 10): 267533438,
     ("hpcg27_104", "hdc", 18): 270161215,
+    ("hpcg27_104", "dia", 1): 302451940,
+    ("hpcg27_104", "dia", 12): 264984757,
+    ("hpcg27_104", "dia", 19): 298418067,
+    ("hpcg27_104", "hdc", 0): 262240530,
+    ("hpcg27_104", "hdc", 1): 302448062,
+    ("hpcg27_104", "hdc", 4): 266981729,
+    ("hpcg27_104", "hdc", 12): 264993295,
+    ("hpcg27_104", "hdc", 19): 298423805,
+    ("hpcg27_104", "hdc", 20): 276069027,
+    ("hpcg27_104", "hdc", 21): 297319433,
 }
 
 
