@@ -1,4 +1,4 @@
-// Streaming probes: the practical HBM ceiling that SpMV kernels are judged
+// Streaming probes: the practical HBM ceiling that SpMV kernels are measured
 // against.  A read-reduce (the access pattern of a matrix sweep: read only,
 // a few bytes written), a copy and a write-only fill, each moving 16 B per
 // lane per access.
