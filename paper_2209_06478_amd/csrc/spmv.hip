@@ -11,9 +11,17 @@
 //        each row with a power-of-two group of lanes; a row longer than 1024
 //        entries gets a workgroup of its own.  Vector variants assign W lanes
 //        to each row.
-//   DIA  one thread per row sweeps the diagonals; the diagonal-major layout
-//        makes every value load and every x load contiguous across a wave.
-//   ELL  one thread per row sweeps the K slots (column-major, coalesced).
+//   DIA  one thread per row sweeps the diagonals in batches; the
+//        diagonal-major layout makes every value load and every x load
+//        contiguous across a wave.  Variants 16-31 instead stage x in LDS
+//        once per cluster of nearby diagonals (k_dia_lds).
+//   ELL  one thread per row sweeps the K slots (column-major, coalesced) in
+//        batches: all column and value loads, then the x gathers.
+//
+// Operands that must vanish (past a row, past the last diagonal, a column
+// outside the matrix) are read from fixed zero / -1 words rather than
+// selected after the load, so every load is unconditional and a lane keeps
+// a batch of loads in flight.
 //   COO  each wave owns a tile of 64*E consecutive entries (E per lane); rows
 //        are combined with a segmented scan across lanes; rows cut by a tile
 //        boundary are finished by a second pass that adds the per-tile
