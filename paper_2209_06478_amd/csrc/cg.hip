@@ -11,7 +11,9 @@
 // and beta bit for bit without a separate reduction launch, and the result
 // does not depend on scheduling.  A device flag stops every later kernel once
 // the solve has converged, broken down or hit maxit; the host reads the
-// state back only every few iterations.
+// state only every few iterations (a one-thread kernel copies it to pinned
+// host memory at the end of each chunk, and the next chunk is usually
+// queued already, so the device does not wait for the host).
 //
 // Mixed precision (iterative refinement): the outer loop keeps x, the
 // residual b - A x, its norm and the update x += d in FP64 (the residual
