@@ -44,9 +44,10 @@ __global__ void __launch_bounds__(CGB) k_cg_init(i64 n, const X *b, const X *q, 
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
-__global__ void __launch_bounds__(CGB) k_cg_init_state(const double *part, CgState *st, double tol, long long maxit) {
+__global__ void __launch_bounds__(CGB) k_cg_init_state(const double *part, int npart, CgState *st, double tol,
+                                                       long long maxit) {
     __shared__ double lds[CGB / WAVE];
-    double rho = reduce_partials(part, lds);
+    double rho = reduce_partials(part, lds, npart);
     if (threadIdx.x == 0) {
         st->rho[0] = rho;
         st->rho[1] = 0;
@@ -141,7 +142,8 @@ __global__ void __launch_bounds__(CGB) k_cg_update_xr(i64 n, X *x, X *r, const X
 }
 
 template <class X, bool NT>
-__global__ void __launch_bounds__(CGB) k_cg_update_p(i64 n, const X *r, X *p, const double *part_rr, CgState *st) {
+__global__ void __launch_bounds__(CGB) k_cg_update_p(i64 n, const X *r, X *p, const double *part_rr, int nrr,
+                                                      CgState *st) {
     __shared__ double lds[CGB / WAVE];
     const i64 hi = slice_hi(n);
     i64 base = slice_lo(n) + threadIdx.x;
@@ -162,7 +164,7 @@ __global__ void __launch_bounds__(CGB) k_cg_update_p(i64 n, const X *r, X *p, co
     const double tol = st->tol, nr0 = st->nr0;
     const long long maxit = st->maxit;
     double rho1;
-    if (wg_done_sum(&st->done, part_rr, CGG, lds, &rho1)) return;
+    if (wg_done_sum(&st->done, part_rr, nrr, lds, &rho1)) return;
     const double rho = ((k - 1) & 1) ? rho_odd : rho_even;
     const double nr = sqrt(rho1);
     int done = 0;
@@ -613,6 +615,11 @@ static CgBuffers cg_buffers(dsm_matrix m, bool ir, Workspace &cgws) {
     return B;
 }
 
+// Workgroups of the vector kernels (= their partials): one per CGB
+// elements up to CGG.  A small system gets a small grid: the kernels stay
+// short and every consumer reduces only that many partials (in the serving
+// mix, full 512-workgroup grids on systems of 10^4-10^5 rows made the two
+// vector kernels 40% of all kernel time).
 static unsigned vec_grid(i64 n) { return (unsigned)std::max<i64>(1, std::min<i64>(CGG, (n + CGB - 1) / CGB)); }
 
 // One CG iteration: SpMV with p.q, x/r update, p update (DIA/ELL sweeps
@@ -623,18 +630,19 @@ template <class X>
 static void enqueue_iteration(dsm_matrix m, X *x, X *r, X *p, X *q, double *part_a, double *part_b, CgState *st,
                               int vdt, hipStream_t s, Workspace &spws) {
     const i64 n = m->nrows;
+    const unsigned G = vec_grid(n);
     int npq = spmv_dot(m, m->P, p, q, vdt, m->variant, s, part_a, &st->iters, &st->done);
     if (npq == 0) {
         spmv(m, m->P, p, q, vdt, m->variant, s, &spws, &st->done);
-        hipLaunchKernelGGL((k_cg_dot_pq<X>), dim3(CGG), dim3(CGB), 0, s, n, p, q, part_a, st);
-        npq = CGG;
+        hipLaunchKernelGGL((k_cg_dot_pq<X>), dim3(G), dim3(CGB), 0, s, n, p, q, part_a, st);
+        npq = (int)G;
     }
     // FP64 vectors are streamed past the caches where they are not reused
     // soon (3-5% per iteration at HPCG 104^3); the FP32 inner loop of IR
     // keeps its vectors cached (its matrix is smaller, the vectors matter more)
     constexpr bool NT = std::is_same<X, double>::value;
-    hipLaunchKernelGGL((k_cg_update_xr<X, NT>), dim3(CGG), dim3(CGB), 0, s, n, x, r, p, q, part_a, npq, part_b, st);
-    hipLaunchKernelGGL((k_cg_update_p<X, NT>), dim3(CGG), dim3(CGB), 0, s, n, r, p, part_b, st);
+    hipLaunchKernelGGL((k_cg_update_xr<X, NT>), dim3(G), dim3(CGB), 0, s, n, x, r, p, q, part_a, npq, part_b, st);
+    hipLaunchKernelGGL((k_cg_update_p<X, NT>), dim3(G), dim3(CGB), 0, s, n, r, p, part_b, (int)G, st);
 }
 
 // Copies the state into slot (seq & 1) of a two-slot host buffer, where seq
@@ -683,9 +691,11 @@ static CgState run_cg(dsm_matrix m, const X *b, X *x, X *r, X *p, X *q, X *p2, d
     X *pbuf[2] = {p, p2};
     // fused: init leaves the r.r partials where the first F1 reads them
     double *init_part = fused ? part_b : part_a;
+    // the fused loop's first sweep reduces CGG partials of the init
+    const unsigned G = fused ? (unsigned)CGG : vec_grid(n);
     spmv(m, m->P, x, q, vdt, m->variant, s, &spws);
-    hipLaunchKernelGGL((k_cg_init<X>), dim3(CGG), dim3(CGB), 0, s, n, b, q, r, p, init_part);
-    hipLaunchKernelGGL(k_cg_init_state, dim3(1), dim3(CGB), 0, s, init_part, st, tol, maxit);
+    hipLaunchKernelGGL((k_cg_init<X>), dim3(G), dim3(CGB), 0, s, n, b, q, r, p, init_part);
+    hipLaunchKernelGGL(k_cg_init_state, dim3(1), dim3(CGB), 0, s, init_part, (int)G, st, tol, maxit);
     DSM_HIP(hipGetLastError());
     // iteration j of a chunk (0-based) has parity (j + 1) & 1
     auto enqueue = [&](int j, hipStream_t ss) {
