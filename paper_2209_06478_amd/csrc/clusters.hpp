@@ -1,0 +1,28 @@
+// Grouping of a DIA matrix's diagonals for the LDS-staged sweep: pure host
+// logic (no HIP), so it can be checked on the CPU.
+//
+// Diagonals (offsets ascending) are cut into consecutive runs of at most
+// `max_k` diagonals whose offsets lie within `max_span` of the run's first
+// offset.  The result is a flat array of {first diagonal, one past the last,
+// lowest offset, highest offset} per run, covering every diagonal once, in
+// order.  A 27-point stencil gives 9 runs of 3 (offsets d-1, d, d+1).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace dsm {
+
+inline std::vector<int32_t> diagonal_clusters(const std::vector<int32_t> &offs, int max_k, int64_t max_span) {
+    std::vector<int32_t> out;
+    const int64_t nd = (int64_t)offs.size();
+    for (int64_t k = 0; k < nd;) {
+        int64_t e = k + 1;
+        while (e < nd && e - k < max_k && (int64_t)offs[e] - offs[k] <= max_span) e++;
+        out.insert(out.end(), {(int32_t)k, (int32_t)e, offs[k], offs[e - 1]});
+        k = e;
+    }
+    return out;
+}
+
+}  // namespace dsm

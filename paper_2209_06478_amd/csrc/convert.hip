@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "clusters.hpp"
 #include "core.hpp"
 
 namespace dsm {
@@ -668,15 +669,10 @@ static void dia_from_csr(dsm_matrix m, const Payload &C, Payload &P, const i32 *
                        slot.as<i32>(), P.offs);
     // diagonal clusters for the LDS-staged sweep (host pass over the offsets)
     if (nd > 0) {
-        std::vector<i32> ho((size_t)nd), hc;
+        std::vector<i32> ho((size_t)nd);
         DSM_HIP(hipMemcpyAsync(ho.data(), P.offs, sizeof(i32) * (size_t)nd, hipMemcpyDeviceToHost, s));
         sync(s);
-        for (i64 k = 0; k < nd;) {
-            i64 e = k + 1;
-            while (e < nd && e - k < DIA_CLUSTER_K && (i64)ho[e] - ho[k] <= DIA_CLUSTER_SPAN) e++;
-            hc.insert(hc.end(), {(i32)k, (i32)e, ho[k], ho[e - 1]});
-            k = e;
-        }
+        const std::vector<i32> hc = diagonal_clusters(ho, DIA_CLUSTER_K, DIA_CLUSTER_SPAN);
         P.nclu = (i64)hc.size() / 4;
         P.clu = (i32 *)P.alloc(ctx, sizeof(i32) * hc.size());
         DSM_HIP(hipMemcpyAsync(P.clu, hc.data(), sizeof(i32) * hc.size(), hipMemcpyHostToDevice, s));
