@@ -85,6 +85,12 @@ constexpr int VU = 4;  // elements per lane per pass in the vector updates
 // NT: x and q are streamed (x is not read again until the next update, q
 // not before the next SpMV rewrites it), so they need not displace the
 // matrix lines the next SpMV may still find in the Infinity Cache.
+//
+// x is updated here and not in the p update, although that would save one
+// read of p: the p update's workgroup 0 sets the done flag, and a workgroup
+// of the same launch that starts after that store exits at once.  Skipping
+// the p update is harmless then (p is dead); skipping a share of the last
+// x += alpha p is not (seen when concurrent solves delayed workgroups).
 template <class X, bool NT>
 __global__ void __launch_bounds__(CGB) k_cg_update_xr(i64 n, X *x, X *r, const X *p, const X *q,
                                                        const double *part_pq, int npq, double *part_rr,
