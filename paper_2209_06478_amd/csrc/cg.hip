@@ -75,12 +75,56 @@ __global__ void __launch_bounds__(CGB) k_cg_dot_pq(i64 n, const X *p, const X *q
     }
 }
 
-constexpr int VU = 4;  // elements per lane per pass in the vector updates
+constexpr int VU = 4;  // loads per vector per lane per pass in the vector updates
 
-// The vector updates load their first VU elements per lane before they
-// reduce the partials their scalar depends on (the loads do not need it), so
-// the latency of the reduction and of the first stream overlap; every load
-// of a pass is issued before any of its stores.
+// L consecutive elements of X in one load: a 16-byte vector for L > 1, the
+// element itself for L = 1.
+template <class X, int L>
+struct Lanes {
+    typedef X T __attribute__((ext_vector_type(L)));
+    static __device__ __forceinline__ X get(const T &v, int e) { return v[e]; }
+};
+template <class X>
+struct Lanes<X, 1> {
+    typedef X T;
+    static __device__ __forceinline__ X get(const T &v, int) { return v; }
+};
+
+template <class X, int L, bool NT>
+__device__ __forceinline__ typename Lanes<X, L>::T ld_lanes(const X *p) {
+    using T = typename Lanes<X, L>::T;
+    if constexpr (NT) return __builtin_nontemporal_load((const T *)p);
+    else return *(const T *)p;
+}
+template <class X, int L, bool NT>
+__device__ __forceinline__ void st_lanes(X *p, typename Lanes<X, L>::T v) {
+    using T = typename Lanes<X, L>::T;
+    if constexpr (NT) __builtin_nontemporal_store(v, (T *)p);
+    else *(T *)p = v;
+}
+
+// Where the L-element loads of this workgroup's slice end: slices start at
+// multiples of blockDim.x (a multiple of L), so only the end of the vector
+// can leave fewer than L elements, handled one by one by the workgroup that
+// owns them.
+template <int L>
+__device__ __forceinline__ i64 lanes_hi(i64 n, i64 hi) {
+    return L == 1 ? hi : min(hi, n / L * L);
+}
+
+// The vector updates load their first VU vectors of L elements per lane
+// before they reduce the partials their scalar depends on (the loads do not
+// need it), so the latency of the reduction and of the first stream overlap;
+// every load of a pass is issued before any of its stores.  They must stay
+// within 128 VGPRs, so that two 512-thread workgroups share a CU and the
+// 512-workgroup grid runs in one round on 256 CUs (the offsets are written
+// out per load: a 64-bit stride variable took the 16-byte-load kernels to
+// 136 VGPRs and one workgroup per CU, slower than one element per load).
+// The host takes
+// L = 2 for FP64 when all vectors are 16-byte aligned (about 2% per
+// iteration at HPCG 104^3 over one element per load), else L = 1.
+// The per-lane sums run over a lane's elements in a different order for
+// different L; each L is deterministic.
 //
 // NT: x and q are streamed (x is not read again until the next update, q
 // not before the next SpMV rewrites it), so they need not displace the
@@ -91,23 +135,25 @@ constexpr int VU = 4;  // elements per lane per pass in the vector updates
 // of the same launch that starts after that store exits at once.  Skipping
 // the p update is harmless then (p is dead); skipping a share of the last
 // x += alpha p is not (seen when concurrent solves delayed workgroups).
-template <class X, bool NT>
+template <class X, bool NT, int L>
 __global__ void __launch_bounds__(CGB) k_cg_update_xr(i64 n, X *x, X *r, const X *p, const X *q,
                                                        const double *part_pq, int npq, double *part_rr,
                                                        CgState *st) {
+    using LT = Lanes<X, L>;
+    using V = typename LT::T;
     __shared__ double lds[CGB / WAVE];
-    const i64 hi = slice_hi(n);
-    i64 base = slice_lo(n) + threadIdx.x;
-    X xv[VU], pv[VU], rv[VU], qv[VU];
+    const i64 lo = slice_lo(n), hi = slice_hi(n), hv = lanes_hi<L>(n, hi);
+    i64 base = lo + (i64)L * threadIdx.x;
+    V xv[VU], pv[VU], rv[VU], qv[VU];
     auto load = [&]() {
 #pragma unroll
         for (int u = 0; u < VU; u++) {
-            const i64 i = base + (i64)u * blockDim.x;
-            if (i < hi) {
-                xv[u] = ld_stream<X, NT>(x + i);
-                pv[u] = p[i];
-                rv[u] = r[i];
-                qv[u] = ld_stream<X, NT>(q + i);
+            const i64 i = base + (i64)u * L * blockDim.x;
+            if (i < hv) {
+                xv[u] = ld_lanes<X, L, NT>(x + i);
+                pv[u] = ld_lanes<X, L, false>(p + i);
+                rv[u] = ld_lanes<X, L, false>(r + i);
+                qv[u] = ld_lanes<X, L, NT>(q + i);
             }
         }
     };
@@ -126,19 +172,29 @@ __global__ void __launch_bounds__(CGB) k_cg_update_xr(i64 n, X *x, X *r, const X
     }
     const X a = (X)(rho / pq);
     double acc = 0;
-    while (base < hi) {
+    while (base < hv) {
 #pragma unroll
         for (int u = 0; u < VU; u++) {
-            const i64 i = base + (i64)u * blockDim.x;
-            if (i < hi) {
-                st_stream<X, NT>(x + i, xv[u] + a * pv[u]);
-                const X ri = rv[u] - a * qv[u];
-                r[i] = ri;
-                acc += (double)ri * (double)ri;
+            const i64 i = base + (i64)u * L * blockDim.x;
+            if (i < hv) {
+                st_lanes<X, L, NT>(x + i, xv[u] + a * pv[u]);
+                const V ri = rv[u] - a * qv[u];
+                st_lanes<X, L, false>(r + i, ri);
+#pragma unroll
+                for (int e = 0; e < L; e++) acc += (double)LT::get(ri, e) * (double)LT::get(ri, e);
             }
         }
-        base += (i64)VU * blockDim.x;
+        base += (i64)VU * L * blockDim.x;
         load();
+    }
+    if (L > 1 && lo < hi && hv < hi) {
+        const i64 i = hv + threadIdx.x;
+        if (i < hi) {
+            x[i] = x[i] + a * p[i];
+            const X ri = r[i] - a * q[i];
+            r[i] = ri;
+            acc += (double)ri * (double)ri;
+        }
     }
     acc = block_sum(acc, lds);
     if (threadIdx.x == 0) {
@@ -147,20 +203,21 @@ __global__ void __launch_bounds__(CGB) k_cg_update_xr(i64 n, X *x, X *r, const X
     }
 }
 
-template <class X, bool NT>
+template <class X, bool NT, int L>
 __global__ void __launch_bounds__(CGB) k_cg_update_p(i64 n, const X *r, X *p, const double *part_rr, int nrr,
                                                       CgState *st) {
+    using V = typename Lanes<X, L>::T;
     __shared__ double lds[CGB / WAVE];
-    const i64 hi = slice_hi(n);
-    i64 base = slice_lo(n) + threadIdx.x;
-    X rv[VU], pv[VU];
+    const i64 lo = slice_lo(n), hi = slice_hi(n), hv = lanes_hi<L>(n, hi);
+    i64 base = lo + (i64)L * threadIdx.x;
+    V rv[VU], pv[VU];
     auto load = [&]() {
 #pragma unroll
         for (int u = 0; u < VU; u++) {
-            const i64 i = base + (i64)u * blockDim.x;
-            if (i < hi) {
-                rv[u] = ld_stream<X, NT>(r + i);
-                pv[u] = p[i];
+            const i64 i = base + (i64)u * L * blockDim.x;
+            if (i < hv) {
+                rv[u] = ld_lanes<X, L, NT>(r + i);
+                pv[u] = ld_lanes<X, L, false>(p + i);
             }
         }
     };
@@ -184,14 +241,18 @@ __global__ void __launch_bounds__(CGB) k_cg_update_p(i64 n, const X *r, X *p, co
     }
     if (done) return;
     const X beta = (X)(rho1 / rho);
-    while (base < hi) {
+    while (base < hv) {
 #pragma unroll
         for (int u = 0; u < VU; u++) {
-            const i64 i = base + (i64)u * blockDim.x;
-            if (i < hi) p[i] = rv[u] + beta * pv[u];
+            const i64 i = base + (i64)u * L * blockDim.x;
+            if (i < hv) st_lanes<X, L, false>(p + i, rv[u] + beta * pv[u]);
         }
-        base += (i64)VU * blockDim.x;
+        base += (i64)VU * L * blockDim.x;
         load();
+    }
+    if (L > 1 && lo < hi && hv < hi) {
+        const i64 i = hv + threadIdx.x;
+        if (i < hi) p[i] = r[i] + beta * p[i];
     }
 }
 
@@ -647,8 +708,18 @@ static void enqueue_iteration(dsm_matrix m, X *x, X *r, X *p, X *q, double *part
     // soon (3-5% per iteration at HPCG 104^3); the FP32 inner loop of IR
     // keeps its vectors cached (its matrix is smaller, the vectors matter more)
     constexpr bool NT = std::is_same<X, double>::value;
-    hipLaunchKernelGGL((k_cg_update_xr<X, NT>), dim3(G), dim3(CGB), 0, s, n, x, r, p, q, part_a, npq, part_b, st);
-    hipLaunchKernelGGL((k_cg_update_p<X, NT>), dim3(G), dim3(CGB), 0, s, n, r, p, part_b, (int)G, st);
+    // FP64: two elements per 16-byte load where every vector allows it; the
+    // FP32 loop keeps one element per load (four per load measured 1% slower)
+    constexpr int L = std::is_same<X, double>::value ? 2 : 1;
+    if (L > 1 && ((uintptr_t)x | (uintptr_t)r | (uintptr_t)p | (uintptr_t)q) % 16 == 0) {
+        hipLaunchKernelGGL((k_cg_update_xr<X, NT, L>), dim3(G), dim3(CGB), 0, s, n, x, r, p, q, part_a, npq, part_b,
+                           st);
+        hipLaunchKernelGGL((k_cg_update_p<X, NT, L>), dim3(G), dim3(CGB), 0, s, n, r, p, part_b, (int)G, st);
+    } else {
+        hipLaunchKernelGGL((k_cg_update_xr<X, NT, 1>), dim3(G), dim3(CGB), 0, s, n, x, r, p, q, part_a, npq, part_b,
+                           st);
+        hipLaunchKernelGGL((k_cg_update_p<X, NT, 1>), dim3(G), dim3(CGB), 0, s, n, r, p, part_b, (int)G, st);
+    }
 }
 
 // Copies the state into slot (seq & 1) of a two-slot host buffer, where seq

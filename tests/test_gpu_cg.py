@@ -114,6 +114,39 @@ def test_cg_nonzero_initial_guess():
     A.close()
 
 
+@pytest.mark.parametrize("offset", [0, 1])
+def test_cg_ragged_sizes_and_unaligned_x(offset):
+    """The FP64 vector updates load two elements per lane where every vector
+    is 16-byte aligned: odd sizes end them with a ragged tail, and an x that
+    starts 8 bytes past a 16-byte boundary (offset 1) takes one element per
+    load.  IR on the same systems covers its FP32 inner loop at odd sizes."""
+    torch, dev = torch_dev()
+    for p in [inputs.hpcg27(7), inputs.banded_spd(1203, 5, seed=4), inputs.hpcg27(1)]:
+        n = p.nrows
+        xo, it, rr, st = oracle.cg(p.row_ptr, p.col, p.val, p.b, tol=1e-10)
+        b = torch.from_numpy(p.b).to(dev)
+        log(f"[cg] {p.name} n={n} x offset {offset}")
+        for fmt, vdt, mode in [("csr", "f64", "f64"), ("dia", "f64", "f64"), ("csr", "f32", "ir")]:
+            A = make_matrix(p)
+            A.convert(fmt, value_dtype=vdt)
+            buf = torch.full((n + 1,), 7.0, dtype=torch.float64, device=dev)
+            buf[offset:offset + n] = 0
+            x, res = A.cg(b, x=buf[offset:offset + n], tol=1e-10, mode=mode)
+            assert (x.data_ptr() % 16 != 0) == (offset == 1)
+            xh = x.cpu().numpy()
+            A.close()
+            assert res["status"] == "converged", (fmt, mode, res)
+            if mode == "f64":
+                assert abs(res["iters"] - it) <= 1, (fmt, res, it)
+                assert oracle.true_relres(p.row_ptr, p.col, p.val, p.b, xh) <= 1.5e-10
+            else:
+                # IR converges for the stored (rounded) values
+                lowvals = oracle.cast_f32(p.val).astype(np.float64)
+                assert oracle.true_relres(p.row_ptr, p.col, lowvals, p.b, xh) <= 1e-10
+            # the element outside the view is untouched
+            assert buf[0 if offset == 1 else n].item() == 7.0
+
+
 def test_cg_rejects_rectangular():
     torch, dev = torch_dev()
     p = problem("rect_empty")
