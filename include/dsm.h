@@ -345,8 +345,11 @@ typedef struct {
 } dsm_cg_result;
 
 /* Solves A x = b for square A.  b and x are FP64 device vectors of length
- * nrows; x holds x0 on entry and the last iterate on return.  The result is
- * filled for OK, NOT_CONVERGED and BREAKDOWN.  Blocking. */
+ * nrows (8-byte aligned; a 16-byte aligned x lets the FP64 loop's vector
+ * updates load two elements at a time, with the same results up to the
+ * order of the per-lane partial sums); x holds x0 on entry and the last
+ * iterate on return.  The result is filled for OK, NOT_CONVERGED and
+ * BREAKDOWN.  Blocking. */
 dsm_status dsm_cg_solve(dsm_matrix m, const double *b, double *x, const dsm_cg_opts *opts,
                         dsm_cg_result *result, void *stream);
 
