@@ -709,7 +709,8 @@ static void enqueue_iteration(dsm_matrix m, X *x, X *r, X *p, X *q, double *part
     // keeps its vectors cached (its matrix is smaller, the vectors matter more)
     constexpr bool NT = std::is_same<X, double>::value;
     // FP64: two elements per 16-byte load where every vector allows it; the
-    // FP32 loop keeps one element per load (four per load measured 1% slower)
+    // FP32 loop keeps one element per load (two or four per load measured
+    // about 1% slower there)
     constexpr int L = std::is_same<X, double>::value ? 2 : 1;
     if (L > 1 && ((uintptr_t)x | (uintptr_t)r | (uintptr_t)p | (uintptr_t)q) % 16 == 0) {
         hipLaunchKernelGGL((k_cg_update_xr<X, NT, L>), dim3(G), dim3(CGB), 0, s, n, x, r, p, q, part_a, npq, part_b,
