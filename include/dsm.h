@@ -349,7 +349,11 @@ typedef struct {
  * updates load two elements at a time, with the same results up to the
  * order of the per-lane partial sums); x holds x0 on entry and the last
  * iterate on return.  The result is filled for OK, NOT_CONVERGED and
- * BREAKDOWN.  Blocking. */
+ * BREAKDOWN.  Blocking.  Two environment switches pick between equivalent
+ * executions of the same iteration: DSM_CG_GRAPH=0 launches the loop
+ * eagerly instead of replaying captured graphs (bitwise the same result),
+ * and DSM_CG_FUSED=1 runs the two-kernel iteration on square DIA/ELL
+ * payloads (slower on MI355X at the HPCG sizes; its rounding differs). */
 dsm_status dsm_cg_solve(dsm_matrix m, const double *b, double *x, const dsm_cg_opts *opts,
                         dsm_cg_result *result, void *stream);
 
