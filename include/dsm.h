@@ -353,7 +353,7 @@ typedef struct {
  * executions of the same iteration: DSM_CG_GRAPH=0 launches the loop
  * eagerly instead of replaying captured graphs (bitwise the same result),
  * and DSM_CG_FUSED=1 runs the two-kernel iteration on square DIA/ELL
- * payloads (slower on MI355X at the HPCG sizes; its rounding differs). */
+ * payloads (slower on MI355X at the HPCG sizes). */
 dsm_status dsm_cg_solve(dsm_matrix m, const double *b, double *x, const dsm_cg_opts *opts,
                         dsm_cg_result *result, void *stream);
 
