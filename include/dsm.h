@@ -297,6 +297,17 @@ typedef struct {
 dsm_status dsm_select(dsm_matrix m, uint32_t candidate_mask, const dsm_select_opts *opts,
                       dsm_select_report *report, void *stream);
 
+/* One profiling run of the active format and kernel variant, the
+ * measurement the selection above makes per candidate (Section V-E:
+ * profiling runs decide the format): `warmup` untimed SpMVs y = A x, then
+ * `reps` SpMVs each bracketed by a pair of events on `stream`; *median_us
+ * receives the median of the bracketed durations in microseconds.  x and y
+ * are as in dsm_spmv (device vectors of vec_dtype, not aliased); y holds
+ * A x afterwards.  reps >= 1, warmup >= 0, otherwise DSM_E_INVALID.
+ * Blocking. */
+dsm_status dsm_time_spmv(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, int32_t warmup, int32_t reps,
+                         double *median_us, void *stream);
+
 /* Drops all cached selections of a context. */
 dsm_status dsm_select_cache_clear(dsm_ctx ctx);
 

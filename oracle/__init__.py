@@ -31,6 +31,17 @@ def build(force=True):
     return LIB_PATH
 
 
+def build_timing(out_dir):
+    """Timing build of the same source for the CPU baseline: -O3
+    -march=native -fopenmp (the compiler may contract multiply-adds), built on
+    the machine that runs it, since -march=native describes that host.  Its
+    results are timed, never used as expected values."""
+    path = os.path.join(out_dir, "liboracle_native.so")
+    cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-o", path, SRC_PATH, "-lm"]
+    subprocess.check_call(cmd)
+    return path
+
+
 _lib = None
 
 
@@ -39,49 +50,60 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = C.CDLL(LIB_PATH)
-        sig = {
-            "orc_set_threads": (_i32, [_i32]),
-            "orc_csr_validate": (_i32, [_i64, _i64, _i64, _p, _p]),
-            "orc_spmv_csr": (None, [_i64, _p, _p, _p, _p, _p]),
-            "orc_spmv_csr_ref": (None, [_i64, _p, _p, _p, _p, _p, _p]),
-            "orc_csr_to_coo": (None, [_i64, _p, _p]),
-            "orc_coo_to_csr": (_i32, [_i64, _i64, _i64, _p, _p, _p, _p, _p, _p]),
-            "orc_spmv_coo": (None, [_i64, _i64, _p, _p, _p, _p, _p]),
-            "orc_dia_count": (_i64, [_i64, _i64, _p, _p, _p]),
-            "orc_csr_to_dia": (None, [_i64, _i64, _p, _p, _p, _i64, _p, _p]),
-            "orc_dia_to_csr": (_i64, [_i64, _i64, _i64, _p, _p, _p, _p, _p]),
-            "orc_spmv_dia": (None, [_i64, _i64, _i64, _p, _p, _p, _p]),
-            "orc_ell_width": (_i32, [_i64, _p]),
-            "orc_csr_to_ell_part": (None, [_i64, _p, _p, _p, _i32, _p, _p]),
-            "orc_ell_to_csr": (_i64, [_i64, _i32, _p, _p, _p, _p, _p]),
-            "orc_spmv_ell": (None, [_i64, _i32, _p, _p, _p, _p]),
-            "orc_hyb_width": (_i32, [_i64, _p]),
-            "orc_hyb_coo_count": (_i64, [_i64, _p, _i32]),
-            "orc_csr_to_hyb": (None, [_i64, _p, _p, _p, _i32, _p, _p, _p, _p, _p]),
-            "orc_hyb_to_csr": (_i64, [_i64, _i32, _p, _p, _i64, _p, _p, _p, _p, _p, _p]),
-            "orc_hdc_true_diags": (_i64, [_i64, _i64, _p, _p, _dbl, _p]),
-            "orc_csr_to_hdc": (_i64, [_i64, _i64, _p, _p, _p, _i64, _p, _p, _p, _p, _p]),
-            "orc_hdc_to_csr": (_i64, [_i64, _i64, _i64, _p, _p, _p, _p, _p, _p, _p, _p]),
-            "orc_cast_f32": (None, [_i64, _p, _p]),
-            "orc_cast_bf16": (None, [_i64, _p, _p]),
-            "orc_bf16_to_f64": (None, [_i64, _p, _p]),
-            "orc_row_stats": (None, [_i64, _p, _p]),
-            "orc_cg": (_i32, [_i64, _p, _p, _p, _p, _p, _dbl, _i64, _p, _p]),
-            "orc_true_relres": (_dbl, [_i64, _p, _p, _p, _p, _p]),
-            "orc_extract_diagonal": (None, [_i64, _i64, _p, _p, _p, _p]),
-            "orc_update_diagonal": (_i64, [_i64, _i64, _p, _p, _p, _p]),
-            "orc_pcg_jacobi": (_i32, [_i64, _p, _p, _p, _p, _p, _dbl, _i64, _p, _p]),
-            "orc_symgs": (_i64, [_i64, _p, _p, _p, _p, _p, _p]),
-            "orc_mg": (None, [_i32, _p, _p, _p, _p, _p, _p, _p, _p]),
-            "orc_pcg_mg": (_i32, [_i32, _p, _p, _p, _p, _p, _p, _p, _p, _dbl, _i64, _p, _p]),
-        }
-        for name, (res, args) in sig.items():
-            f = getattr(L, name)
-            f.restype = res
-            f.argtypes = args
-        _lib = L
+        _lib = _load(LIB_PATH)
     return _lib
+
+
+def use_build(path):
+    """Routes this module's functions to another build of oracle.c (the
+    timing build); use_build(None) returns to the check build."""
+    global _lib
+    _lib = _load(path) if path else None
+
+
+def _load(path):
+    L = C.CDLL(path)
+    sig = {
+        "orc_set_threads": (_i32, [_i32]),
+        "orc_csr_validate": (_i32, [_i64, _i64, _i64, _p, _p]),
+        "orc_spmv_csr": (None, [_i64, _p, _p, _p, _p, _p]),
+        "orc_spmv_csr_ref": (None, [_i64, _p, _p, _p, _p, _p, _p]),
+        "orc_csr_to_coo": (None, [_i64, _p, _p]),
+        "orc_coo_to_csr": (_i32, [_i64, _i64, _i64, _p, _p, _p, _p, _p, _p]),
+        "orc_spmv_coo": (None, [_i64, _i64, _p, _p, _p, _p, _p]),
+        "orc_dia_count": (_i64, [_i64, _i64, _p, _p, _p]),
+        "orc_csr_to_dia": (None, [_i64, _i64, _p, _p, _p, _i64, _p, _p]),
+        "orc_dia_to_csr": (_i64, [_i64, _i64, _i64, _p, _p, _p, _p, _p]),
+        "orc_spmv_dia": (None, [_i64, _i64, _i64, _p, _p, _p, _p]),
+        "orc_ell_width": (_i32, [_i64, _p]),
+        "orc_csr_to_ell_part": (None, [_i64, _p, _p, _p, _i32, _p, _p]),
+        "orc_ell_to_csr": (_i64, [_i64, _i32, _p, _p, _p, _p, _p]),
+        "orc_spmv_ell": (None, [_i64, _i32, _p, _p, _p, _p]),
+        "orc_hyb_width": (_i32, [_i64, _p]),
+        "orc_hyb_coo_count": (_i64, [_i64, _p, _i32]),
+        "orc_csr_to_hyb": (None, [_i64, _p, _p, _p, _i32, _p, _p, _p, _p, _p]),
+        "orc_hyb_to_csr": (_i64, [_i64, _i32, _p, _p, _i64, _p, _p, _p, _p, _p, _p]),
+        "orc_hdc_true_diags": (_i64, [_i64, _i64, _p, _p, _dbl, _p]),
+        "orc_csr_to_hdc": (_i64, [_i64, _i64, _p, _p, _p, _i64, _p, _p, _p, _p, _p]),
+        "orc_hdc_to_csr": (_i64, [_i64, _i64, _i64, _p, _p, _p, _p, _p, _p, _p, _p]),
+        "orc_cast_f32": (None, [_i64, _p, _p]),
+        "orc_cast_bf16": (None, [_i64, _p, _p]),
+        "orc_bf16_to_f64": (None, [_i64, _p, _p]),
+        "orc_row_stats": (None, [_i64, _p, _p]),
+        "orc_cg": (_i32, [_i64, _p, _p, _p, _p, _p, _dbl, _i64, _p, _p]),
+        "orc_true_relres": (_dbl, [_i64, _p, _p, _p, _p, _p]),
+        "orc_extract_diagonal": (None, [_i64, _i64, _p, _p, _p, _p]),
+        "orc_update_diagonal": (_i64, [_i64, _i64, _p, _p, _p, _p]),
+        "orc_pcg_jacobi": (_i32, [_i64, _p, _p, _p, _p, _p, _dbl, _i64, _p, _p]),
+        "orc_symgs": (_i64, [_i64, _p, _p, _p, _p, _p, _p]),
+        "orc_mg": (None, [_i32, _p, _p, _p, _p, _p, _p, _p, _p]),
+        "orc_pcg_mg": (_i32, [_i32, _p, _p, _p, _p, _p, _p, _p, _p, _dbl, _i64, _p, _p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
 
 
 def _ptr(a):

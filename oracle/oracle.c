@@ -580,9 +580,13 @@ static double dot_lr(i64 n, const double *a, const double *b)
     return s;
 }
 
-static void spmv_serial(i64 n, const i32 *rp, const i32 *col, const double *val,
-                        const double *x, double *y)
+/* q = A x by definition.  Rows are independent and each is summed by one
+ * thread in ascending column order, so the result does not depend on the
+ * number of threads; only the dot products (dot_lr) stay sequential. */
+static void spmv_rows(i64 n, const i32 *rp, const i32 *col, const double *val,
+                      const double *x, double *y)
 {
+#pragma omp parallel for schedule(static)
     for (i64 i = 0; i < n; i++) {
         double s = 0.0;
         for (i64 k = rp[i]; k < rp[i + 1]; k++) s = s + val[k] * x[col[k]];
@@ -596,7 +600,7 @@ int orc_cg(i64 n, const i32 *rp, const i32 *col, const double *val, const double
     double *r = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     double *p = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     double *q = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    spmv_serial(n, rp, col, val, x, q);
+    spmv_rows(n, rp, col, val, x, q);
     for (i64 i = 0; i < n; i++) r[i] = b[i] - q[i];
     for (i64 i = 0; i < n; i++) p[i] = r[i];
     double rho = dot_lr(n, r, r);
@@ -610,7 +614,7 @@ int orc_cg(i64 n, const i32 *rp, const i32 *col, const double *val, const double
         status = 2;
     } else {
         while (it < maxit) {
-            spmv_serial(n, rp, col, val, p, q);
+            spmv_rows(n, rp, col, val, p, q);
             it++;
             double pq = dot_lr(n, p, q);
             if (!(pq > 0.0) || !isfinite(pq)) {
@@ -618,8 +622,11 @@ int orc_cg(i64 n, const i32 *rp, const i32 *col, const double *val, const double
                 break;
             }
             double alpha = rho / pq;
-            for (i64 i = 0; i < n; i++) x[i] = x[i] + alpha * p[i];
-            for (i64 i = 0; i < n; i++) r[i] = r[i] - alpha * q[i];
+#pragma omp parallel for schedule(static)
+            for (i64 i = 0; i < n; i++) {
+                x[i] = x[i] + alpha * p[i];
+                r[i] = r[i] - alpha * q[i];
+            }
             double rho1 = dot_lr(n, r, r);
             if (!isfinite(rho1)) {
                 status = 2;
@@ -631,6 +638,7 @@ int orc_cg(i64 n, const i32 *rp, const i32 *col, const double *val, const double
                 break;
             }
             double beta = rho1 / rho;
+#pragma omp parallel for schedule(static)
             for (i64 i = 0; i < n; i++) p[i] = r[i] + beta * p[i];
             rho = rho1;
         }
@@ -718,7 +726,7 @@ int orc_pcg_jacobi(i64 n, const i32 *rp, const i32 *col, const double *val, cons
     for (i64 i = 0; i < n; i++)
         if (dg[i] == 0.0) status = 3;
     if (status == 3) goto out;
-    spmv_serial(n, rp, col, val, x, q);
+    spmv_rows(n, rp, col, val, x, q);
     for (i64 i = 0; i < n; i++) r[i] = b[i] - q[i];
     for (i64 i = 0; i < n; i++) z[i] = r[i] / dg[i];
     for (i64 i = 0; i < n; i++) p[i] = z[i];
@@ -734,7 +742,7 @@ int orc_pcg_jacobi(i64 n, const i32 *rp, const i32 *col, const double *val, cons
         goto out;
     }
     while (it < maxit) {
-        spmv_serial(n, rp, col, val, p, q);
+        spmv_rows(n, rp, col, val, p, q);
         it++;
         double pq = dot_lr(n, p, q);
         if (!(pq > 0.0) || !isfinite(pq)) {
@@ -847,7 +855,7 @@ static void mg_level(int l, int nlev, const i64 *n, const i32 *const *rp, const 
     double *ax = (double *)malloc(sizeof(double) * (size_t)(nf > 0 ? nf : 1));
     double *rc = (double *)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
     double *xc = (double *)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
-    spmv_serial(nf, rp[l], col[l], val[l], x, ax);
+    spmv_rows(nf, rp[l], col[l], val[l], x, ax);
     for (i64 i = 0; i < nc; i++) rc[i] = r[f2c[l][i]] - ax[f2c[l][i]];
     mg_level(l + 1, nlev, n, rp, col, val, ord, f2c, rc, xc);
     for (i64 i = 0; i < nc; i++) x[f2c[l][i]] = x[f2c[l][i]] + xc[i];
@@ -882,7 +890,7 @@ int orc_pcg_mg(int nlev, const i64 *n, const i32 *const *rp, const i32 *const *c
     for (int l = 0; l < nlev; l++)
         if (count_bad_diag(n[l], rp[l], col[l], val[l])) status = 3;
     if (status == 3) goto out;
-    spmv_serial(nn, rp[0], col[0], val[0], x, q);
+    spmv_rows(nn, rp[0], col[0], val[0], x, q);
     for (i64 i = 0; i < nn; i++) r[i] = b[i] - q[i];
     double nr0 = sqrt(dot_lr(nn, r, r));
     if (nr0 == 0.0) {
@@ -904,7 +912,7 @@ int orc_pcg_mg(int nlev, const i64 *n, const i32 *const *rp, const i32 *const *c
             for (i64 i = 0; i < nn; i++) p[i] = z[i] + beta * p[i];
         }
         rho = rho1;
-        spmv_serial(nn, rp[0], col[0], val[0], p, q);
+        spmv_rows(nn, rp[0], col[0], val[0], p, q);
         it++;
         double pq = dot_lr(nn, p, q);
         if (!(pq > 0.0) || !isfinite(pq)) {

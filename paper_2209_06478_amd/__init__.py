@@ -285,6 +285,21 @@ class Matrix:
                                          _stream(stream)), "dsm_spmv_accumulate")
         return out
 
+    def time_spmv(self, x, out=None, warmup=3, reps=20, stream=None):
+        """Median SpMV time in microseconds over `reps` event-bracketed
+        launches after `warmup` untimed ones (the selection's protocol)."""
+        torch = _torch()
+        i = self.info()
+        vdt = _vec_dtype(x)
+        xp = _dev_ptr(x, i["ncols"], "x")
+        if out is None:
+            out = torch.empty(i["nrows"], dtype=x.dtype, device=x.device)
+        yp = _dev_ptr(out, i["nrows"], "out")
+        med = C.c_double()
+        _check(lib().dsm_time_spmv(self.h, xp, yp, vdt, int(warmup), int(reps), C.byref(med), _stream(stream)),
+               "dsm_time_spmv")
+        return med.value
+
     def select(self, mask=ALL_FORMATS, warmup=3, reps=20, use_cache=True, tune_variant=True, vec_dtype="f64",
                value_dtype="f64", max_pad_ratio=16.0, bytes_prefilter=2.0, target=0, stream=None):
         """target 0: time device-wide SpMV; 1: time one-workgroup CG solves."""

@@ -97,6 +97,7 @@ SIGNATURES = {
     "dsm_select_opts_default": (None, [C.POINTER(SelectOpts)]),
     "dsm_select": (_st, [_p, C.c_uint32, C.POINTER(SelectOpts), C.POINTER(SelectReport), _p]),
     "dsm_select_cache_clear": (_st, [_p]),
+    "dsm_time_spmv": (_st, [_p, _p, _p, C.c_int, C.c_int32, C.c_int32, C.POINTER(C.c_double), _p]),
     "dsm_cg_opts_default": (None, [C.POINTER(CgOpts)]),
     "dsm_cg_solve": (_st, [_p, _p, _p, C.POINTER(CgOpts), C.POINTER(CgResult), _p]),
     "dsm_cg_solve_batched": (_st, [C.c_int32, C.POINTER(_p), C.POINTER(_p), C.POINTER(_p), C.POINTER(CgOpts),

@@ -448,6 +448,20 @@ DSM_API dsm_status dsm_select(dsm_matrix m, uint32_t candidate_mask, const dsm_s
     });
 }
 
+DSM_API dsm_status dsm_time_spmv(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, int32_t warmup,
+                                 int32_t reps, double *median_us, void *stream) {
+    return guard([&] {
+        DSM_CHECK(m && m->ctx && median_us, DSM_E_INVALID, "null argument");
+        DSM_CHECK((x || m->ncols == 0) && (y || m->nrows == 0), DSM_E_INVALID, "null vector");
+        DSM_CHECK(x != y || m->nrows == 0, DSM_E_INVALID, "x and y must not alias");
+        DSM_CHECK(reps >= 1 && warmup >= 0, DSM_E_INVALID, "reps must be >= 1 and warmup >= 0");
+        DSM_HIP(hipSetDevice(m->ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        *median_us = time_spmv(m, m->P, m->variant, x, y, vec_dtype, warmup, reps, s);
+        m->last_stream = s;
+    });
+}
+
 DSM_API dsm_status dsm_select_cache_clear(dsm_ctx ctx) {
     return guard([&] {
         DSM_CHECK(ctx, DSM_E_INVALID, "null context");

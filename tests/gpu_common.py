@@ -94,3 +94,55 @@ def row_scaled_err(y, yref, scale):
         return 0.0
     d = np.abs(y - yref)
     return float(np.max(np.where(d == 0, 0.0, d / np.maximum(scale, 1e-300))))
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_cg(name, tol=1e-10):
+    """The oracle's FP64 CG on a named workload: (x, iters, relres, status)."""
+    p = problem(name)
+    return oracle.cg(p.row_ptr, p.col, p.val, p.b, tol=tol)
+
+
+# the kernel variants the timed selection tries per format (csrc/select.cpp)
+SELECT_VARIANTS = {"csr": [0, 7, 2, 3, 4, 5, 6], "dia": [0, 1, 2, 4, 8, 10, 12, 16, 18, 20, 19, 21],
+                   "hdc": [0, 1, 2, 4, 8, 10, 12, 16, 18, 20, 19, 21], "ell": [0, 1, 2, 4, 8, 10, 12],
+                   "hyb": [0, 1, 2, 4, 8, 10, 12], "coo": [0]}
+
+
+def median_launch_us(A, x, y, warmup, reps):
+    """The library's profiling run (the selection's own protocol: warm-up,
+    then event-bracketed launches back to back, median)."""
+    return A.time_spmv(x, out=y, warmup=warmup, reps=reps)
+
+
+def selection_retime(p, A, rep, value_dtype="f64", rounds=3, warmup=3, reps=20):
+    """Re-times the selection's outcome against fresh conversions of every
+    candidate it timed (status 0), every (format, variant) pair the same way:
+    `rounds` interleaved rounds, each a median of `reps` event-bracketed
+    launches after `warmup` untimed ones (the selector's own protocol, run by
+    the library so that no host overhead sits between the launches), and the
+    median over rounds.  Returns (chosen us, best us, best label)."""
+    torch, dev = torch_dev()
+    x = torch.ones(p.ncols, dtype=torch.float64, device=dev)
+    y = torch.empty(p.nrows, dtype=torch.float64, device=dev)
+    pairs = []
+    mats = []
+    for f, st in rep["status"].items():
+        if st != 0:
+            continue
+        B = make_matrix(p)
+        B.convert(f, value_dtype=value_dtype)
+        mats.append(B)
+        for v in SELECT_VARIANTS[f]:
+            pairs.append((f, v, B))
+    times = {(f, v): [] for f, v, _ in pairs}
+    for _ in range(rounds):
+        for f, v, B in pairs:
+            B.variant = v
+            times[(f, v)].append(median_launch_us(B, x, y, warmup, reps))
+    med = {k: float(np.median(t)) for k, t in times.items()}
+    for B in mats:
+        B.close()
+    best = min(med, key=med.get)
+    chosen = med[(rep["chosen"], rep["chosen_variant"])]
+    return chosen, med[best], f"{best[0]} v{best[1]}"

@@ -82,9 +82,6 @@ def test_cg_special_cases():
     assert res["status"] == "converged" and res["iters"] == 0 and not x.any()
     x, res = A.cg(torch.from_numpy(p.b).to(dev), maxit=3)
     assert res["status"] == "not_converged" and res["iters"] == 3
-    xo = np.zeros(p.nrows)
-    for _ in range(1):
-        pass
     bb = p.b.copy()
     bb[7] = np.nan
     x, res = A.cg(torch.from_numpy(bb).to(dev))

@@ -43,13 +43,15 @@ def test_budget_exhaustion_keeps_old_format():
     ctx0.close()
     ctx = dsm.Context(0, hbm_budget=int(csr_bytes * 1.5))
     A = dsm.Matrix.from_csr(ctx, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
+    before = ctx.bytes_in_use()
+    assert before >= A.info()["bytes"]
     with pytest.raises(dsm.DsmError) as e:
         A.convert("coo")  # COO + CSR together exceed the budget
     assert e.value.status == dsm.L.E_NOMEM
     assert A.format == "csr"
+    assert ctx.bytes_in_use() == before  # the failed build released what it had taken
     y = A.spmv(torch.from_numpy(x).to(dev)).cpu().numpy()
     assert row_scaled_err(y, yref, scale) <= 1e-14
-    assert ctx.bytes_in_use() == A.info()["bytes"] + 0 or ctx.bytes_in_use() >= A.info()["bytes"]
     A.close()
     ctx.close()
 

@@ -255,3 +255,20 @@ def test_true_relres():
     r = p.b - dense(p) @ x
     ref = np.linalg.norm(r) / np.linalg.norm(p.b)
     assert abs(oracle.true_relres(p.row_ptr, p.col, p.val, p.b, x) - ref) <= 1e-12 * ref
+
+
+def test_cg_independent_of_thread_count():
+    """The oracle's CG runs its SpMV rows and element-wise updates on OpenMP
+    threads and its dot products sequentially: the iterate is bitwise the
+    same on one thread and on several."""
+    p = inputs.banded_spd(3000, 12, seed=4)
+    saved = oracle.set_threads(0)
+    try:
+        oracle.set_threads(1)
+        x1, it1, rr1, st1 = oracle.cg(p.row_ptr, p.col, p.val, p.b, tol=1e-12)
+        oracle.set_threads(max(2, os.cpu_count() or 2))
+        x8, it8, rr8, st8 = oracle.cg(p.row_ptr, p.col, p.val, p.b, tol=1e-12)
+    finally:
+        oracle.set_threads(saved)
+    assert st1 == st8 == "converged" and it1 == it8 and rr1 == rr8
+    assert np.array_equal(x1.view(np.uint64), x8.view(np.uint64))
