@@ -386,8 +386,11 @@ dsm_status dsm_cg_solve_batched(int32_t count, const dsm_matrix *mats, const dou
 /* ------------------------------------------------------------------ */
 typedef struct {
     int32_t slots;           /* requests in flight at once (default 64)        */
-    size_t hbm_budget;       /* bytes of matrices + workspaces in flight
-                                (0 = the context's budget or unlimited)       */
+    size_t hbm_budget;       /* bound on the matrix bytes of the requests in
+                                flight plus the device workspaces the workers
+                                hold (kept between requests, grown to powers
+                                of two); 0 = the context's budget, or no bound
+                                when the context has none                    */
     int32_t streams;         /* HIP streams for large requests (default 4)     */
     int64_t small_rows;      /* requests with at most this many rows go to the
                                 persistent batched kernel (default 4096, at
@@ -403,13 +406,19 @@ typedef struct {
     double finish_s;   /* result known on the host                    */
 } dsm_timestamps;
 
-/* Creates a server with its own scheduler thread. */
+/* Creates a server with `streams` worker threads, each with its own HIP
+ * stream (default priority) and its own workspaces. */
 dsm_status dsm_server_create(dsm_ctx ctx, const dsm_server_opts *opts, dsm_server *out);
 
 /* Queues a solve of m x = b (b, x device FP64 vectors; x holds x0).  The
  * matrix and both vectors must stay alive and untouched until the request
- * completes.  Requests whose footprint exceeds the server budget fail with
- * DSM_E_NOMEM at submit.  *ticket identifies the request. */
+ * completes.  A request that could not run on an idle server within the
+ * budget (its matrix bytes plus the workspaces it needs) fails with
+ * DSM_E_NOMEM at submit; otherwise it waits in arrival order until a slot
+ * and budget are free.  Workspace allocations go through the context's
+ * budget too: one that fails sends the request back to the head of the
+ * queue while other requests are in flight, and fails it with DSM_E_NOMEM
+ * (in its result) when none is.  *ticket identifies the request. */
 dsm_status dsm_server_submit(dsm_server s, dsm_matrix m, const double *b, double *x,
                              const dsm_cg_opts *opts, uint64_t *ticket);
 
@@ -425,6 +434,24 @@ dsm_status dsm_server_wait(dsm_server s, uint64_t ticket, dsm_cg_result *result,
 
 /* Seconds on the server's clock (the clock of dsm_timestamps). */
 double dsm_server_now(dsm_server s);
+
+typedef struct {
+    uint64_t submitted;          /* requests accepted by dsm_server_submit       */
+    uint64_t completed;          /* requests finished (any status)               */
+    uint64_t budget_waits;       /* requests that reached the head of the queue
+                                    and waited there for budget with a slot and
+                                    a worker free                                */
+    uint64_t requeued;           /* units of work sent back to the queue after a
+                                    failed workspace allocation                  */
+    uint64_t peak_charged_bytes; /* most matrix + workspace bytes charged at once */
+    uint64_t workspace_bytes;    /* device workspace the workers hold now        */
+    double busy_s;               /* time with at least one unit of work running
+                                    (from its start to its result on the host)  */
+    double elapsed_s;            /* time since dsm_server_create                 */
+} dsm_server_stats;
+
+/* Counters of the server since its creation.  Non-blocking. */
+dsm_status dsm_server_get_stats(dsm_server s, dsm_server_stats *out);
 
 /* Waits for every queued request, stops the scheduler and frees the server. */
 dsm_status dsm_server_destroy(dsm_server s);

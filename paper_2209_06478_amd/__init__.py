@@ -422,6 +422,11 @@ class Server:
     def now(self):
         return lib().dsm_server_now(self.h)
 
+    def stats(self):
+        st = L.ServerStats()
+        _check(lib().dsm_server_get_stats(self.h, C.byref(st)), "dsm_server_get_stats")
+        return {k: getattr(st, k) for k, _ in L.ServerStats._fields_}
+
     def close(self):
         if self.h:
             _check(lib().dsm_server_destroy(self.h), "dsm_server_destroy")

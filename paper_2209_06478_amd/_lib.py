@@ -66,7 +66,13 @@ class Timestamps(C.Structure):
     _fields_ = [("arrival_s", C.c_double), ("start_s", C.c_double), ("finish_s", C.c_double)]
 
 
-STRUCTS = {"dsm_convert_opts": ConvertOpts, "dsm_info": Info, "dsm_export_bufs": ExportBufs,
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("budget_waits", C.c_uint64),
+                ("requeued", C.c_uint64), ("peak_charged_bytes", C.c_uint64), ("workspace_bytes", C.c_uint64),
+                ("busy_s", C.c_double), ("elapsed_s", C.c_double)]
+
+
+STRUCTS = {"dsm_server_stats": ServerStats, "dsm_convert_opts": ConvertOpts, "dsm_info": Info, "dsm_export_bufs": ExportBufs,
            "dsm_select_opts": SelectOpts, "dsm_select_report": SelectReport, "dsm_cg_opts": CgOpts,
            "dsm_cg_result": CgResult, "dsm_server_opts": ServerOpts, "dsm_timestamps": Timestamps}
 
@@ -108,6 +114,7 @@ SIGNATURES = {
     "dsm_server_poll": (_st, [_p, C.c_uint64, C.POINTER(CgResult), C.POINTER(Timestamps)]),
     "dsm_server_wait": (_st, [_p, C.c_uint64, C.POINTER(CgResult), C.POINTER(Timestamps)]),
     "dsm_server_now": (C.c_double, [_p]),
+    "dsm_server_get_stats": (_st, [_p, C.POINTER(ServerStats)]),
     "dsm_server_destroy": (_st, [_p]),
     "dsm_stream_probe": (_st, [C.c_int32, _p, _p, C.c_int64, _p]),
     "dsm_mg_create": (_st, [_p, C.c_int32, C.POINTER(_p), C.POINTER(_p), C.POINTER(_p), _p, C.POINTER(_p)]),

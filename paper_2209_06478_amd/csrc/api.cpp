@@ -47,17 +47,19 @@ static void drop_graph(Workspace &w) {
     w.graph_key.clear();
 }
 
-void *ws_get(dsm_ctx ctx, Workspace &w, size_t bytes) {
+void *ws_get(dsm_ctx ctx, Workspace &w, size_t bytes, hipStream_t s) {
     if (w.bytes >= bytes && w.p) return w.p;
     drop_graph(w);
     if (w.p) {
-        DSM_HIP(hipDeviceSynchronize());
+        DSM_HIP(hipStreamSynchronize(s));
+        if (w.stream) DSM_HIP(hipStreamSynchronize(w.stream));
         dev_free(ctx, w.p, w.bytes);
         w.p = nullptr;
         w.bytes = 0;
     }
-    w.p = dev_alloc(ctx, bytes);
-    w.bytes = bytes;
+    const size_t b = w.grow_pow2 ? ws_round(bytes) : bytes;
+    w.p = dev_alloc(ctx, b);
+    w.bytes = b;
     return w.p;
 }
 

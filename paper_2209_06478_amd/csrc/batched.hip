@@ -240,7 +240,10 @@ static int default_lanes(const dsm_matrix_s *m, const Payload &P) {
 
 static size_t vec_bytes(i64 n) { return ((size_t)std::max<i64>(n, 1) * 8 + 255) & ~(size_t)255; }
 
-size_t batch_request_bytes(i64 n) { return 3 * vec_bytes(n) + sizeof(BReq) + sizeof(BRes) + 512; }
+// Arena bytes of one batch: a fixed part (the work counter and the 256-byte
+// rounding of the descriptor and result arrays) plus one share per request.
+size_t batch_request_bytes(i64 n) { return 3 * vec_bytes(n) + sizeof(BReq) + sizeof(BRes); }
+size_t batch_arena_fixed() { return 1536; }
 
 static BReq make_req(const dsm_matrix_s *m, const Payload &P, int lanes) {
     BReq R{};
@@ -266,9 +269,9 @@ static void launch_reqs(dsm_ctx ctx, std::vector<BReq> &hreq, std::vector<BRes> 
                         hipStream_t s) {
     const int count = (int)hreq.size();
     if (count == 0) return;
-    size_t bytes = 1024 + count * (sizeof(BReq) + sizeof(BRes)) + 512;
-    for (auto &R : hreq) bytes += 3 * vec_bytes(R.n);
-    char *base = (char *)ws_get(ctx, arena, bytes);
+    size_t bytes = batch_arena_fixed();
+    for (auto &R : hreq) bytes += batch_request_bytes(R.n);
+    char *base = (char *)ws_get(ctx, arena, bytes, s);
     auto take = [&](size_t sz) {
         char *p = base;
         base += (sz + 255) & ~(size_t)255;

@@ -651,9 +651,9 @@ size_t cg_workspace_bytes(i64 n, bool ir) {
     return bytes;
 }
 
-static CgBuffers cg_buffers(dsm_matrix m, bool ir, Workspace &cgws) {
+static CgBuffers cg_buffers(dsm_matrix m, bool ir, Workspace &cgws, hipStream_t s) {
     const size_t n = (size_t)std::max<i64>(m->nrows, 1);
-    char *base = (char *)ws_get(m->ctx, cgws, cg_workspace_bytes(m->nrows, ir));
+    char *base = (char *)ws_get(m->ctx, cgws, cg_workspace_bytes(m->nrows, ir), s);
     CgBuffers B;
     auto take = [&](size_t sz) {
         char *p = base;
@@ -858,7 +858,10 @@ void cg_solve_ws(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o,
               "unknown CG mode");
     DSM_CHECK(!ir || m->P.vdt != DSM_F64, DSM_E_UNSUPPORTED,
               "iterative refinement needs F32 or BF16 matrix values (convert with value_dtype)");
-    CgBuffers B = cg_buffers(m, ir, cgws);
+    CgBuffers B = cg_buffers(m, ir, cgws, s);
+    // the SpMV scratch is sized before anything is enqueued (no allocation
+    // while an iteration chunk is captured)
+    if (const size_t sb = spmv_scratch_bytes(m, m->P, DSM_F64)) ws_get(m->ctx, spws, sb, s);
     if (n == 0) {
         R.status = DSM_OK;
         *res = R;

@@ -26,6 +26,8 @@ struct dsm_ctx_s {
     std::map<std::string, std::pair<int, int>> select_cache;  // fingerprint -> (format, variant)
 };
 
+#include "admission.hpp"
+
 namespace dsm {
 
 // Device memory charged against the context budget.
@@ -92,6 +94,7 @@ struct Workspace {
     hipStream_t stream = nullptr;
     void *host = nullptr;         // pinned host staging (hipHostMalloc)
     void *events[2] = {nullptr, nullptr};  // hipEvent_t, for the staging slots
+    bool grow_pow2 = false;       // grow to the next power of two (ws_round)
 };
 
 }  // namespace dsm
@@ -109,8 +112,11 @@ struct dsm_matrix_s {
 
 namespace dsm {
 
-// Grows (never shrinks) a workspace; contents are not preserved.
-void *ws_get(dsm_ctx ctx, Workspace &w, size_t bytes);
+// Grows (never shrinks) a workspace; contents are not preserved.  A
+// workspace is used on one stream at a time: before its memory is replaced,
+// the stream `s` of the call and the workspace's own replay stream are
+// synchronised (not the whole device).
+void *ws_get(dsm_ctx ctx, Workspace &w, size_t bytes, hipStream_t s);
 void ws_release(dsm_ctx ctx, Workspace &w);
 // Releases a workspace's graph, stream, events and pinned host staging;
 // its device memory stays.
@@ -166,6 +172,9 @@ void diagonal_op(dsm_matrix m, double *d, int mode, hipStream_t s);
 int spmv_dot(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant, hipStream_t s,
              double *part, long long *count, const int *stop);
 // Algorithmic bytes one SpMV must move (x read once, y written once).
+// Device scratch one SpMV of this payload needs with vec_dtype vectors (the
+// COO tile carries of COO and HYB; 0 for the other formats).
+size_t spmv_scratch_bytes(const dsm_matrix_s *m, const Payload &P, int vec_dtype);
 double spmv_bytes(const dsm_matrix_s *m, const Payload &P, int vec_dtype);
 // Number of CSR kernel variants (index 0 = adaptive) and of DIA/ELL sweep
 // variants (tile order x row groups per thread x paired rows).
@@ -189,6 +198,7 @@ size_t cg_workspace_bytes(i64 n, bool ir);
 // of one solve of `P` with `lanes` (CSR) for `iters` iterations (us).
 bool batch_eligible(const dsm_matrix_s *m, i64 small_rows);
 size_t batch_request_bytes(i64 n);
+size_t batch_arena_fixed();
 double time_batched_solve(dsm_matrix m, const Payload &P, int lanes, int iters, hipStream_t s);
 struct BatchJob {
     std::vector<dsm_matrix> mats;

@@ -668,7 +668,7 @@ static void coo_launch(dsm_matrix m, i64 nnz, const i32 *row, const i32 *col, co
         return;
     }
     const i64 ntiles = (nnz + COO_TE - 1) / COO_TE;
-    X *part = (X *)ws_get(m->ctx, scratch ? *scratch : m->ws, sizeof(X) * (size_t)(2 * ntiles));
+    X *part = (X *)ws_get(m->ctx, scratch ? *scratch : m->ws, sizeof(X) * (size_t)(2 * ntiles), s);
     X *head = part, *tail = part + ntiles;
     const unsigned g = grid_for(ntiles, SB / WAVE);
     if (acc) {
@@ -844,6 +844,13 @@ int spmv_dot(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, in
     if (vdt == DSM_F64)
         return spmv_dot_typed<double>(m, P, (const double *)x, (double *)y, variant, s, part, count, stop);
     return spmv_dot_typed<float>(m, P, (const float *)x, (float *)y, variant, s, part, count, stop);
+}
+
+size_t spmv_scratch_bytes(const dsm_matrix_s *m, const Payload &P, int vec_dtype) {
+    (void)m;
+    if (!(P.fmt == DSM_COO || P.fmt == DSM_HYB) || P.coo_nnz == 0) return 0;
+    const i64 ntiles = (P.coo_nnz + COO_TE - 1) / COO_TE;
+    return dtype_size(vec_dtype) * (size_t)(2 * ntiles);
 }
 
 double spmv_bytes(const dsm_matrix_s *m, const Payload &P, int vec_dtype) {
