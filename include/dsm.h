@@ -522,6 +522,15 @@ dsm_status dsm_pcg_mg_solve(dsm_mg mg, const double *b, double *x, const dsm_cg_
  * give DSM_E_INVALID before anything is launched. */
 dsm_status dsm_stream_probe(int32_t mode, const void *src, void *dst, int64_t bytes, void *stream);
 
+/* The gather ceiling of irregular SpMV: reads idx[0, n) (int32, device) and
+ * x[idx[k]] (FP64, device, xlen entries; an index outside [0, xlen) reads
+ * nothing and adds 0) and writes DSM_PROBE_PARTIALS FP64 partial sums of the
+ * gathered values to part (device).  With idx = a CSR column array it moves
+ * the x-operand traffic of that matrix's SpMV alone.  Asynchronous on
+ * `stream`; bad arguments give DSM_E_INVALID before anything is launched. */
+dsm_status dsm_gather_probe(const double *x, int64_t xlen, const int32_t *idx, int64_t n, double *part,
+                            void *stream);
+
 #ifdef __cplusplus
 }
 #endif

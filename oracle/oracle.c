@@ -252,6 +252,11 @@ i64 orc_dia_to_csr(i64 nrows, i64 ncols, i64 ndiag, const i32 *offsets, const do
     return nz;
 }
 
+/* y = A x over the DIA slots.  A slot holding +0 or -0 is no entry of the
+ * matrix (padding and a stored zero cannot be told apart, the reading the
+ * conversion out of DIA follows too), so its x operand does not enter the
+ * row sum: with finite x that changes nothing, and an infinite or NaN x_j
+ * reaches only the rows that store a nonzero in column j, as in CSR. */
 void orc_spmv_dia(i64 nrows, i64 ncols, i64 ndiag, const i32 *offsets, const double *vals,
                   const double *x, double *y)
 {
@@ -259,7 +264,8 @@ void orc_spmv_dia(i64 nrows, i64 ncols, i64 ndiag, const i32 *offsets, const dou
         double s = 0.0;
         for (i64 k = 0; k < ndiag; k++) {
             i64 j = i + offsets[k];
-            if (j >= 0 && j < ncols) s = s + vals[k * nrows + i] * x[j];
+            double a = (j >= 0 && j < ncols) ? vals[k * nrows + i] : 0.0;
+            if (a != 0.0) s = s + a * x[j];
         }
         y[i] = s;
     }

@@ -21,7 +21,7 @@ from ._lib import (COO, CSR, DIA, ELL, HYB, HDC, F64, F32, BF16, FORMATS, FORMAT
                    CG_F64, CG_IR, CG_JACOBI, PROBE_PARTIALS)
 
 __all__ = ["Context", "Matrix", "Server", "DsmError", "lib", "COO", "CSR", "DIA", "ELL", "HYB", "HDC",
-           "F64", "F32", "BF16", "FORMATS", "DTYPES", "cg_batched", "stream_probe", "Multigrid"]
+           "F64", "F32", "BF16", "FORMATS", "DTYPES", "cg_batched", "stream_probe", "gather_probe", "Multigrid"]
 
 ALL_FORMATS = (1 << 6) - 1
 
@@ -384,6 +384,18 @@ def stream_probe(mode, dst, src=None, stream=None):
             raise ValueError("copy needs a src at least as large as dst")
     sp = C.c_void_p(src.data_ptr()) if src is not None else C.c_void_p(None)
     _check(lib().dsm_stream_probe(m, sp, C.c_void_p(dst.data_ptr()), nbytes, _stream(stream)), "dsm_stream_probe")
+
+
+def gather_probe(x, idx, part, stream=None):
+    """Sums x[idx[k]] (FP64 x, int32 idx, CUDA tensors) into
+    PROBE_PARTIALS FP64 partials: the gather traffic of an irregular SpMV."""
+    torch = _torch()
+    if x.dtype != torch.float64 or idx.dtype != torch.int32 or part.dtype != torch.float64:
+        raise TypeError("x and part must be float64, idx int32")
+    if part.numel() < L.PROBE_PARTIALS or not (x.is_cuda and idx.is_cuda and part.is_cuda):
+        raise ValueError(f"CUDA tensors needed, part of at least {L.PROBE_PARTIALS} elements")
+    _check(lib().dsm_gather_probe(C.c_void_p(x.data_ptr()), x.numel(), C.c_void_p(idx.data_ptr()), idx.numel(),
+                                  C.c_void_p(part.data_ptr()), _stream(stream)), "dsm_gather_probe")
 
 
 class Server:

@@ -117,6 +117,7 @@ SIGNATURES = {
     "dsm_server_get_stats": (_st, [_p, C.POINTER(ServerStats)]),
     "dsm_server_destroy": (_st, [_p]),
     "dsm_stream_probe": (_st, [C.c_int32, _p, _p, C.c_int64, _p]),
+    "dsm_gather_probe": (_st, [_p, C.c_int64, _p, C.c_int64, _p, _p]),
     "dsm_mg_create": (_st, [_p, C.c_int32, C.POINTER(_p), C.POINTER(_p), C.POINTER(_p), _p, C.POINTER(_p)]),
     "dsm_mg_destroy": (_st, [_p]),
     "dsm_mg_symgs": (_st, [_p, C.c_int32, _p, _p, _p]),

@@ -188,6 +188,21 @@ class Admission {
     bool should_shrink(int worker) const { return held_bytes(worker) > 0 && head_blocked_by_budget(worker); }
 
     uint64_t head_id() const { return q_.empty() ? 0 : q_.front().id; }
+
+    // True when the head can never get in as things stand: it does not fit
+    // for lack of budget, nothing is in flight (no end of a unit will free
+    // anything) and no worker holds workspace to give back.  Only possible
+    // when the bytes counted from outside grew after the head was submitted.
+    bool head_stuck(int worker) const {
+        return in_flight_ == 0 && held_total_ == 0 && head_blocked_by_budget(worker);
+    }
+
+    // Removes the head without admitting it (to fail it).
+    Item pop_head() {
+        Item it = q_.front();
+        q_.pop_front();
+        return it;
+    }
     size_t peak_charged() const { return peak_; }
     bool empty() const { return q_.empty(); }
     size_t queued() const { return q_.size(); }

@@ -61,9 +61,48 @@ __global__ void __launch_bounds__(PB) k_probe_write(d2 *__restrict__ dst, i64 n)
     for (i64 i = b0 + threadIdx.x; i < b1; i += PB) dst[i] = z;
 }
 
+// Random-gather probe: the x-operand traffic of an irregular SpMV without
+// the rest of it.  Lane-contiguous index loads (PU per lane in flight), then
+// one 8-byte gather per index; an index outside [0, xlen) reads nothing.
+__global__ void __launch_bounds__(PB) k_probe_gather(const double *__restrict__ x, i64 xlen,
+                                                     const i32 *__restrict__ idx, i64 n, double *__restrict__ part) {
+    i64 b0, b1;
+    chunk_of(n, b0, b1);
+    double s = 0.0;
+    i64 i = b0 + threadIdx.x;
+    for (; i + (PU - 1) * PB < b1; i += PU * PB) {
+        i32 j[PU];
+#pragma unroll
+        for (int u = 0; u < PU; u++) j[u] = idx[i + u * PB];
+        double v[PU];
+#pragma unroll
+        for (int u = 0; u < PU; u++) v[u] = (u64)(i64)j[u] < (u64)xlen ? x[j[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < PU; u++) s += v[u];
+    }
+    for (; i < b1; i += PB) {
+        const i32 j = idx[i];
+        s += (u64)(i64)j < (u64)xlen ? x[j] : 0.0;
+    }
+    __shared__ double lds[PB / WAVE];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 }  // namespace dsm
 
 using namespace dsm;
+
+DSM_API dsm_status dsm_gather_probe(const double *x, int64_t xlen, const int32_t *idx, int64_t n, double *part,
+                                    void *stream) {
+    return guard([&] {
+        DSM_CHECK(n >= 0 && xlen >= 0, DSM_E_INVALID, "negative length");
+        DSM_CHECK(part && (idx || n == 0) && (x || xlen == 0), DSM_E_INVALID, "null buffer");
+        hipLaunchKernelGGL(k_probe_gather, dim3(DSM_PROBE_PARTIALS), dim3(PB), 0, (hipStream_t)stream, x, xlen,
+                           idx, n, part);
+        DSM_HIP(hipGetLastError());
+    });
+}
 
 DSM_API dsm_status dsm_stream_probe(int32_t mode, const void *src, void *dst, int64_t bytes, void *stream) {
     return guard([&] {

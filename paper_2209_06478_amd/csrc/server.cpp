@@ -125,6 +125,19 @@ static void worker_main(dsm_server s, int w) {
                     s->budget_waits++;
                     s->last_blocked = s->adm.head_id();
                 }
+                if (s->adm.head_stuck(w)) {
+                    // nothing in flight or held can make room: fail it
+                    const Admission::Item it = s->adm.pop_head();
+                    auto &r = s->reqs[it.id];
+                    r.res = dsm_cg_result{};
+                    r.res.status = DSM_E_NOMEM;
+                    r.error = DSM_E_NOMEM;
+                    r.ts.start_s = r.ts.finish_s = s->now();
+                    r.done = true;
+                    s->completed++;
+                    s->cv_done.notify_all();
+                    continue;
+                }
                 if (s->adm.should_shrink(w)) {
                     // idle, and what this worker holds keeps the head out:
                     // give it back (nothing of this worker is in flight)

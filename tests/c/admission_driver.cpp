@@ -233,6 +233,15 @@ int main() {
         CHECK(ids(u3) == std::vector<uint64_t>({3}) && a.charged() == 10 * K);
         finish(a, u3);
     }
+    {  // a head that cannot get in while nothing runs and nothing is held
+        Admission a(8, 4 * K, 8, 1, 0, false);
+        a.set_external(K);
+        a.push(large(1, 0, 2 * K));
+        CHECK(!a.head_stuck(0));
+        a.set_external(3 * K);  // the context filled up after the submit
+        CHECK(a.head_stuck(0) && a.take(0, &small).empty());
+        CHECK(a.pop_head().id == 1 && a.empty() && !a.head_stuck(0));
+    }
     if (fails) return 1;
     std::printf("admission driver ok\n");
     return 0;

@@ -42,3 +42,20 @@ def test_probe_rejects_bad_arguments():
     assert L.dsm_stream_probe(dsm.L.PROBE_WRITE, None, odd, 32, s) == dsm.L.E_INVALID  # misaligned
     torch.cuda.synchronize()
     assert int((a != 0).sum()) == 0
+
+
+@pytest.mark.parametrize("n,xlen", [(0, 10), (5, 3), (1000, 777), (4096 * 256 * 16 + 11, 100003)])
+def test_gather_probe_sums(n, xlen):
+    """The gather probe adds x[idx[k]] over every index in range and nothing
+    for the ones outside [0, xlen) (negative and too large alike)."""
+    torch, dev = torch_dev()
+    import numpy as np
+    import inputs
+    x = inputs.uniform_vector(xlen, seed=n + 1)
+    idx = (inputs.uniform(5, n, np.arange(n, dtype=np.uint64)) * (xlen + 20)).astype(np.int64) - 10
+    ok = (idx >= 0) & (idx < xlen)
+    expect = float(np.sum(x[idx[ok]])) if n else 0.0
+    part = torch.full((dsm.PROBE_PARTIALS,), float("nan"), dtype=torch.float64, device=dev)
+    dsm.gather_probe(torch.from_numpy(x).to(dev), torch.from_numpy(idx.astype(np.int32)).to(dev), part)
+    torch.cuda.synchronize()
+    assert abs(float(part.sum()) - expect) <= 1e-12 * max(n, 1)

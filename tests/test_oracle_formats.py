@@ -184,3 +184,27 @@ def test_banded_hdc_keeps_only_main_diagonal():
     offs = oracle.hdc_true_diags(p.nrows, p.ncols, p.row_ptr, p.col, 0.5)
     assert offs.tolist() == [0]
     assert oracle.dia_offsets(p.nrows, p.ncols, p.row_ptr, p.col).tolist() == list(range(-8, 9))
+
+
+def test_dia_spmv_nonfinite_x_reaches_only_stored_entries():
+    """A DIA zero slot (padding, or an entry the matrix does not store) is no
+    entry: infinite and NaN x values reach exactly the rows that store a
+    nonzero in their column, as the CSR definition gives, and the other rows
+    keep their finite sums.  A dense product would spread 0 * Inf = NaN."""
+    p = inputs.random_sparse(60, 70, 0.08, 31)
+    x = inputs.uniform_vector(p.ncols, seed=4) - 0.5
+    x[[3, 40]] = [np.inf, np.nan]
+    x[p.ncols - 1] = -np.inf
+    offs, dv = oracle.csr_to_dia(p.nrows, p.ncols, p.row_ptr, p.col, p.val)
+    y_dia = oracle.spmv_dia(p.nrows, p.ncols, offs, dv, x)
+    y_csr = oracle.spmv_csr(p.row_ptr, p.col, p.val, x)
+    np.testing.assert_array_equal(y_dia, y_csr)  # NaN where NaN, same infinities
+    touch = np.array([bool(set(p.col[p.row_ptr[i]:p.row_ptr[i + 1]]) & {3, 40, p.ncols - 1})
+                      for i in range(p.nrows)])
+    assert touch.any() and (~touch).any()
+    assert np.all(np.isfinite(y_dia[~touch])) and not np.any(np.isfinite(y_dia[touch]))
+    dense = np.zeros((p.nrows, p.ncols))
+    for i in range(p.nrows):
+        dense[i, p.col[p.row_ptr[i]:p.row_ptr[i + 1]]] = p.val[p.row_ptr[i]:p.row_ptr[i + 1]]
+    with np.errstate(invalid="ignore"):
+        assert np.all(np.isnan(dense @ x))  # every row meets 0 * Inf in the dense product
