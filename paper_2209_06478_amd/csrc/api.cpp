@@ -54,11 +54,18 @@ void *ws_get(dsm_ctx ctx, Workspace &w, size_t bytes, hipStream_t s) {
         DSM_HIP(hipStreamSynchronize(s));
         if (w.stream) DSM_HIP(hipStreamSynchronize(w.stream));
         dev_free(ctx, w.p, w.bytes);
+        if (w.live) *w.live -= w.bytes;
         w.p = nullptr;
         w.bytes = 0;
     }
     const size_t b = w.grow_pow2 ? ws_round(bytes) : bytes;
-    w.p = dev_alloc(ctx, b);
+    if (w.live) *w.live += b;
+    try {
+        w.p = dev_alloc(ctx, b);
+    } catch (...) {
+        if (w.live) *w.live -= b;
+        throw;
+    }
     w.bytes = b;
     return w.p;
 }
@@ -77,7 +84,10 @@ void ws_release_host(Workspace &w) {
 
 void ws_release(dsm_ctx ctx, Workspace &w) {
     ws_release_host(w);
-    if (w.p) dev_free(ctx, w.p, w.bytes);
+    if (w.p) {
+        dev_free(ctx, w.p, w.bytes);
+        if (w.live) *w.live -= w.bytes;
+    }
     w.p = nullptr;
     w.bytes = 0;
 }

@@ -95,6 +95,11 @@ struct Workspace {
     void *host = nullptr;         // pinned host staging (hipHostMalloc)
     void *events[2] = {nullptr, nullptr};  // hipEvent_t, for the staging slots
     bool grow_pow2 = false;       // grow to the next power of two (ws_round)
+    // When set, device bytes this workspace holds are added here before they
+    // are allocated and taken off after they are freed, so a reader that
+    // subtracts it from the context's bytes in use never counts a workspace
+    // as memory of someone else.
+    std::atomic<size_t> *live = nullptr;
 };
 
 }  // namespace dsm

@@ -45,8 +45,7 @@ struct dsm_server_s {
     dsm_server_s(const dsm_server_opts &o, dsm_ctx c)
         : ctx(c), opts(o), budget(o.hbm_budget ? o.hbm_budget : c->budget),
           ctx_mode(o.hbm_budget == 0 && c->budget != 0),
-          adm(o.slots, budget, o.batch_max, o.streams, dsm::batch_arena_fixed(), !ctx_mode),
-          ws_worker(o.streams, 0) {}
+          adm(o.slots, budget, o.batch_max, o.streams, dsm::batch_arena_fixed(), !ctx_mode) {}
     dsm_ctx ctx = nullptr;
     dsm_server_opts opts{};
     size_t budget = 0;
@@ -62,21 +61,21 @@ struct dsm_server_s {
     int running = 0;        // units of work between their start and their result
     double busy_since = 0, busy_s = 0;
 
-    std::vector<size_t> ws_worker;  // workspace bytes each worker holds (settled)
-    size_t ws_actual = 0;
+    // Device bytes the workers' workspaces hold at this moment, updated by
+    // the allocations themselves (a workspace grown during a unit of work is
+    // counted before the unit settles).  Allocation adds before and freeing
+    // subtracts after the context's own count changes, so the difference
+    // below can only undercount the bytes held by others, never count a
+    // workspace twice (which would refuse requests that fit).
+    std::atomic<size_t> ws_live{0};
 
     // guarded by mu
     void refresh() {
         if (!ctx_mode) return;
-        const size_t in = ctx->in_use.load();
-        adm.set_external(in > ws_actual ? in - ws_actual : 0);
+        const size_t in = ctx->in_use.load(), ws = ws_live.load();
+        adm.set_external(in > ws ? in - ws : 0);
     }
-    void settle(int w, const size_t *cap) {
-        const size_t tot = cap[0] + cap[1] + cap[2];
-        ws_actual = ws_actual - ws_worker[w] + tot;
-        ws_worker[w] = tot;
-        adm.settle(w, cap);
-    }
+    void settle(int w, const size_t *cap) { adm.settle(w, cap); }
     void unit_started(double t) {
         if (running++ == 0) busy_since = t;
     }
@@ -105,6 +104,7 @@ static void worker_main(dsm_server s, int w) {
     (void)hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
     Workspace arena, cgws, spws;
     arena.grow_pow2 = cgws.grow_pow2 = spws.grow_pow2 = true;  // sizes the admission predicts
+    arena.live = cgws.live = spws.live = &s->ws_live;
     size_t cap[WS_KINDS];
     for (;;) {
         std::vector<Admission::Item> take;
@@ -136,6 +136,7 @@ static void worker_main(dsm_server s, int w) {
                     r.done = true;
                     s->completed++;
                     s->cv_done.notify_all();
+                    s->cv_work.notify_all();  // a new head, maybe for another worker
                     continue;
                 }
                 if (s->adm.should_shrink(w)) {
@@ -296,7 +297,10 @@ DSM_API dsm_status dsm_server_submit(dsm_server s, dsm_matrix m, const double *b
         s->adm.push(it);
         s->submitted++;
         *ticket = id;
-        s->cv_work.notify_one();
+        // every idle worker looks: the head may fit only on a worker that
+        // already holds large enough workspaces, and a worker that cannot
+        // take it waits without waking the others
+        s->cv_work.notify_all();
     });
 }
 

@@ -142,6 +142,21 @@ int main() {
         CHECK(ids(u) == std::vector<uint64_t>({2}) && a.charged() == 5 * K);
         finish(a, u);
     }
+    {  // the head fits only on the worker already holding its workspace:
+       // an empty worker cannot take it and has nothing to give back, so
+       // the server must wake every worker when a request arrives
+        Admission a(64, 100 + 4 * K, 256, 2);
+        a.push(large(1, 100, 3 * K));
+        auto u = a.take(1, &small);
+        settle(a, 1, 0, 4 * K, 0);
+        finish(a, u);
+        a.push(large(2, 100, 3 * K));
+        CHECK(a.take(0, &small).empty() && a.head_blocked_by_budget(0));
+        CHECK(!a.should_shrink(0) && !a.head_stuck(0));
+        u = a.take(1, &small);
+        CHECK(ids(u) == std::vector<uint64_t>({2}) && a.held_bytes() == 4 * K);
+        finish(a, u);
+    }
     {  // a failed allocation sends the unit back to the head while others
        // run; the queue waits for one of them to finish
         Admission a(64, 0, 256, 2);
