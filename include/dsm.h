@@ -227,6 +227,20 @@ dsm_status dsm_update_diagonal(dsm_matrix m, const double *d, void *stream);
  * there, as in dsm_convert).  Asynchronous on `stream`. */
 dsm_status dsm_spmv(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, void *stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): y = A x
+ * exactly as dsm_spmv (same kernels, same result bit for bit), but no call
+ * allocates or frees memory.  The only device memory beyond A, x and y,
+ * the COO part's per-tile partials (COO, and HYB's COO part), lives in a
+ * static 2 MiB device buffer per GPU, set up when the first context on
+ * that GPU is created and held until the process ends.  F64 vectors take
+ * 16 bytes per 256 COO entries, F32 vectors 8: a COO part beyond about
+ * 33.5M entries (F64) or 67M (F32) gives DSM_E_NOMEM and launches nothing.
+ * Every call on one GPU shares that buffer: calls that overlap on one GPU
+ * (other streams, other threads, other contexts) race on it and must be
+ * serialised by the caller.  Asynchronous on `stream`. */
+dsm_status dsm_spmv_noalloc(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, void *stream);
+
 /* y += A x, otherwise as dsm_spmv.  Lets a matrix split into parts held in
  * different formats - a rank's regular local block and its irregular ghost
  * block (Section V-A, Fig. 2; Section V-E) - add into one y. */

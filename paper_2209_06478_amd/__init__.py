@@ -275,6 +275,17 @@ class Matrix:
         _check(lib().dsm_spmv(self.h, xp, yp, vdt, _stream(stream)), "dsm_spmv")
         return out
 
+    def spmv_noalloc(self, x, out, stream=None):
+        """out = A x through the allocation-free entry point (the caller
+        passes out; the library allocates nothing)."""
+        i = self.info()
+        vdt = _vec_dtype(x)
+        if out.dtype != x.dtype:
+            raise TypeError("x and out must have the same dtype")
+        _check(lib().dsm_spmv_noalloc(self.h, _dev_ptr(x, i["ncols"], "x"), _dev_ptr(out, i["nrows"], "out"), vdt,
+                                      _stream(stream)), "dsm_spmv_noalloc")
+        return out
+
     def spmv_accumulate(self, x, out, stream=None):
         """out += A x (device vectors of the same dtype)."""
         i = self.info()

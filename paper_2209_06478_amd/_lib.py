@@ -98,6 +98,7 @@ SIGNATURES = {
     "dsm_update_diagonal": (_st, [_p, _p, _p]),
     "dsm_spmv": (_st, [_p, _p, _p, C.c_int, _p]),
     "dsm_spmv_accumulate": (_st, [_p, _p, _p, C.c_int, _p]),
+    "dsm_spmv_noalloc": (_st, [_p, _p, _p, C.c_int, _p]),
     "dsm_set_variant": (_st, [_p, C.c_int32]),
     "dsm_get_variant": (_st, [_p, C.POINTER(C.c_int32)]),
     "dsm_select_opts_default": (None, [C.POINTER(SelectOpts)]),

@@ -49,6 +49,7 @@ static void drop_graph(Workspace &w) {
 
 void *ws_get(dsm_ctx ctx, Workspace &w, size_t bytes, hipStream_t s) {
     if (w.bytes >= bytes && w.p) return w.p;
+    DSM_CHECK(!w.fixed, DSM_E_NOMEM, "workspace of fixed size too small");
     drop_graph(w);
     if (w.p) {
         DSM_HIP(hipStreamSynchronize(s));
@@ -132,6 +133,7 @@ DSM_API dsm_status dsm_ctx_create(int device, size_t hbm_budget_bytes, dsm_ctx *
         DSM_HIP(hipGetDeviceProperties(&prop, device));
         DSM_CHECK(std::string(prop.gcnArchName).rfind("gfx950", 0) == 0, DSM_E_UNSUPPORTED,
                   std::string("library built for gfx950, device is ") + prop.gcnArchName);
+        noalloc_scratch_init(device);
         auto *c = new dsm_ctx_s();
         c->device = device;
         c->budget = hbm_budget_bytes;
@@ -421,6 +423,17 @@ DSM_API dsm_status dsm_spmv(dsm_matrix m, const void *x, void *y, dsm_dtype vec_
         DSM_CHECK(x != y || m->nrows == 0, DSM_E_INVALID, "x and y must not alias");
         hipStream_t s = (hipStream_t)stream;
         spmv(m, m->P, x, y, vec_dtype, m->variant, s);
+        m->last_stream = s;
+    });
+}
+
+DSM_API dsm_status dsm_spmv_noalloc(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, void *stream) {
+    return guard([&] {
+        check_matrix(m);
+        DSM_CHECK((x || m->ncols == 0) && (y || m->nrows == 0), DSM_E_INVALID, "null vector");
+        DSM_CHECK(x != y || m->nrows == 0, DSM_E_INVALID, "x and y must not alias");
+        hipStream_t s = (hipStream_t)stream;
+        spmv_noalloc(m, x, y, vec_dtype, s);
         m->last_stream = s;
     });
 }

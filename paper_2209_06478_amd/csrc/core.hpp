@@ -100,6 +100,9 @@ struct Workspace {
     // subtracts it from the context's bytes in use never counts a workspace
     // as memory of someone else.
     std::atomic<size_t> *live = nullptr;
+    // Memory the workspace does not own (the allocation-free entry point's
+    // static buffer): ws_get never frees, replaces or grows it.
+    bool fixed = false;
 };
 
 }  // namespace dsm
@@ -166,6 +169,12 @@ StructFeatures structure_features(dsm_matrix m, const Payload &C, double theta, 
 // COO tile partials (the matrix's own workspace when null).  When `stop`
 // is given, every kernel returns at once if *stop is non-zero (the CG loop's
 // convergence flag).  With `acc` the product is added to y (y += A x).
+// Allocation-free SpMV: the COO tile partials live in a static device
+// buffer of NOALLOC_SCRATCH_BYTES whose per-device address is taken once per
+// device at context creation (noalloc_scratch_init, with the device current).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)2 << 20;
+void noalloc_scratch_init(int device);
+void spmv_noalloc(dsm_matrix m, const void *x, void *y, int vdt, hipStream_t s);
 void spmv(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant,
           hipStream_t s, Workspace *scratch = nullptr, const int *stop = nullptr, bool acc = false);
 // diag.hip: mode 0 extracts A(i, i) into d (FP64, 0 where absent); mode 1

@@ -846,6 +846,49 @@ int spmv_dot(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, in
     return spmv_dot_typed<float>(m, P, (const float *)x, (float *)y, variant, s, part, count, stop);
 }
 
+// ---------------------------------------------------------------- allocation-free entry
+// The COO pass's per-tile partials for callers that cannot allocate: a
+// static device array, one copy per device, of NOALLOC_SCRATCH_BYTES.  Host
+// code never uses the array's name as an address: the address of each
+// device's copy is taken with hipGetSymbolAddress once, with that device
+// current, and kept in g_noalloc_ptr.  Nothing in it needs clearing: every
+// tile writes its two partials before the fix-up pass reads them.
+static __device__ __align__(256) unsigned char g_noalloc_scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_noalloc_mu;
+static void *g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+void noalloc_scratch_init(int device) {
+    DSM_CHECK(device >= 0 && device < NOALLOC_MAX_DEVICES, DSM_E_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr[device]) return;
+    void *p = nullptr;
+    DSM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(g_noalloc_scratch)));
+    DSM_CHECK(p != nullptr, DSM_E_DEVICE, "no device address for the static scratch buffer");
+    g_noalloc_ptr[device] = p;
+}
+
+void spmv_noalloc(dsm_matrix m, const void *x, void *y, int vdt, hipStream_t s) {
+    const int dev = m->ctx->device;
+    void *p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        p = g_noalloc_ptr[dev];
+    }
+    DSM_CHECK(p != nullptr, DSM_E_INVALID, "static scratch not set up for this device");
+    DSM_CHECK(vdt == DSM_F64 || vdt == DSM_F32, DSM_E_UNSUPPORTED, "spmv: vectors must be F64 or F32");
+    const size_t need = spmv_scratch_bytes(m, m->P, vdt);
+    DSM_CHECK(need <= NOALLOC_SCRATCH_BYTES, DSM_E_NOMEM,
+              "allocation-free SpMV: the COO part needs " + std::to_string(need) +
+                  " bytes of scratch, more than the static buffer's " + std::to_string(NOALLOC_SCRATCH_BYTES));
+    Workspace w;
+    w.p = p;
+    w.bytes = NOALLOC_SCRATCH_BYTES;
+    w.fixed = true;
+    spmv(m, m->P, x, y, vdt, m->variant, s, &w, nullptr, false);
+}
+
 size_t spmv_scratch_bytes(const dsm_matrix_s *m, const Payload &P, int vec_dtype) {
     (void)m;
     if (!(P.fmt == DSM_COO || P.fmt == DSM_HYB) || P.coo_nnz == 0) return 0;
