@@ -253,8 +253,11 @@ dsm_status dsm_spmv_accumulate(dsm_matrix m, const void *x, void *y, dsm_dtype v
  * log2 of the row groups per thread (1, 2, 4, 4), bit 3 = groups of two
  * adjacent rows fetched with double-width loads.  DIA and HDC also take
  * bit 4 (16..31): x is staged in LDS once per cluster of up to 3 nearby
- * diagonals instead of gathered per diagonal (bits 0-3 keep their meaning).
- * COO: 0.  Set by dsm_select or directly; an out-of-range value gives
+ * diagonals instead of gathered per diagonal (bits 0-3 keep their meaning),
+ * and bit 5 (32..63): the stored values are loaded with a nontemporal hint
+ * (faster when the sweep starts with cold caches, slower back to back when
+ * the matrix would stay in the Infinity Cache; identical results; the dot
+ * form inside CG uses plain loads).  COO: 0.  Set by dsm_select or directly; an out-of-range value gives
  * DSM_E_INVALID. */
 dsm_status dsm_set_variant(dsm_matrix m, int32_t variant);
 dsm_status dsm_get_variant(dsm_matrix m, int32_t *variant);
@@ -284,6 +287,16 @@ typedef struct {
                               workgroup, the path dsm_cg_solve_batched takes
                               (candidates CSR/DIA/ELL; for CSR the lanes per
                               row are tuned too)                              */
+    int64_t flush_bytes;   /* 0 (default): warm timing, back-to-back SpMVs as
+                              an iterative solver runs them.  > 0 (target 0
+                              only): cold timing for an SpMV that finds none
+                              of its operands in the caches - before every
+                              timed SpMV the selection reads a device buffer
+                              of this many bytes (allocated for the call
+                              and counted in the context's budget; more than
+                              L2 plus the 256 MB Infinity Cache, e.g. 1 GiB),
+                              and each time is kernel-only, as
+                              dsm_spmv_kernel_time measures it              */
 } dsm_select_opts;
 
 void dsm_select_opts_default(dsm_select_opts *o);
@@ -321,6 +334,17 @@ dsm_status dsm_select(dsm_matrix m, uint32_t candidate_mask, const dsm_select_op
  * Blocking. */
 dsm_status dsm_time_spmv(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, int32_t warmup, int32_t reps,
                          double *median_us, void *stream);
+
+/* Kernel-only duration of one SpMV y = A x (as dsm_spmv) in the active
+ * format and variant: *us receives the time from the start of its first
+ * kernel to the end of its last, from HIP events that its launches record
+ * themselves (hipExtLaunchKernel), so neither separate event packets nor
+ * the gap after work queued earlier on `stream` are counted; 0 when there
+ * is nothing to launch.  Work queued earlier on `stream` (for example a read
+ * that evicts the caches) runs first and is not part of the time.
+ * Blocking. */
+dsm_status dsm_spmv_kernel_time(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, double *us,
+                                void *stream);
 
 /* Drops all cached selections of a context. */
 dsm_status dsm_select_cache_clear(dsm_ctx ctx);

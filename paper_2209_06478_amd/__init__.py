@@ -296,6 +296,18 @@ class Matrix:
                                          _stream(stream)), "dsm_spmv_accumulate")
         return out
 
+    def kernel_time(self, x, out, stream=None):
+        """out = A x; returns the kernel-only duration of that SpMV in
+        microseconds (events recorded by its own launches)."""
+        i = self.info()
+        vdt = _vec_dtype(x)
+        if out.dtype != x.dtype:
+            raise TypeError("x and out must have the same dtype")
+        us = C.c_double(0)
+        _check(lib().dsm_spmv_kernel_time(self.h, _dev_ptr(x, i["ncols"], "x"), _dev_ptr(out, i["nrows"], "out"), vdt,
+                                          C.byref(us), _stream(stream)), "dsm_spmv_kernel_time")
+        return us.value
+
     def time_spmv(self, x, out=None, warmup=3, reps=20, stream=None):
         """Median SpMV time in microseconds over `reps` event-bracketed
         launches after `warmup` untimed ones (the selection's protocol)."""
@@ -312,12 +324,15 @@ class Matrix:
         return med.value
 
     def select(self, mask=ALL_FORMATS, warmup=3, reps=20, use_cache=True, tune_variant=True, vec_dtype="f64",
-               value_dtype="f64", max_pad_ratio=16.0, bytes_prefilter=2.0, target=0, stream=None):
-        """target 0: time device-wide SpMV; 1: time one-workgroup CG solves."""
+               value_dtype="f64", max_pad_ratio=16.0, bytes_prefilter=2.0, target=0, flush_bytes=0, stream=None):
+        """target 0: time device-wide SpMV; 1: time one-workgroup CG solves.
+        flush_bytes > 0: cold timing (a read of that many bytes before each
+        timed SpMV, kernel-only times)."""
         o = L.SelectOpts()
         lib().dsm_select_opts_default(C.byref(o))
         o.warmup, o.reps, o.use_cache, o.tune_variant = warmup, reps, int(use_cache), int(tune_variant)
         o.target = int(target)
+        o.flush_bytes = int(flush_bytes)
         o.vec_dtype, o.value_dtype = _dt(vec_dtype), _dt(value_dtype)
         o.max_pad_ratio, o.bytes_prefilter = max_pad_ratio, bytes_prefilter
         r = L.SelectReport()

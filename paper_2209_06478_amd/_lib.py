@@ -38,7 +38,7 @@ class ExportBufs(C.Structure):
 class SelectOpts(C.Structure):
     _fields_ = [("warmup", C.c_int32), ("reps", C.c_int32), ("use_cache", C.c_int32), ("tune_variant", C.c_int32),
                 ("vec_dtype", C.c_int), ("value_dtype", C.c_int), ("max_pad_ratio", C.c_double),
-                ("bytes_prefilter", C.c_double), ("target", C.c_int32)]
+                ("bytes_prefilter", C.c_double), ("target", C.c_int32), ("flush_bytes", C.c_int64)]
 
 
 class SelectReport(C.Structure):
@@ -99,6 +99,7 @@ SIGNATURES = {
     "dsm_spmv": (_st, [_p, _p, _p, C.c_int, _p]),
     "dsm_spmv_accumulate": (_st, [_p, _p, _p, C.c_int, _p]),
     "dsm_spmv_noalloc": (_st, [_p, _p, _p, C.c_int, _p]),
+    "dsm_spmv_kernel_time": (_st, [_p, _p, _p, C.c_int, C.POINTER(C.c_double), _p]),
     "dsm_set_variant": (_st, [_p, C.c_int32]),
     "dsm_get_variant": (_st, [_p, C.POINTER(C.c_int32)]),
     "dsm_select_opts_default": (None, [C.POINTER(SelectOpts)]),

@@ -673,7 +673,7 @@ static void dia_from_csr(dsm_matrix m, const Payload &C, Payload &P, const i32 *
         DSM_HIP(hipMemcpyAsync(ho.data(), P.offs, sizeof(i32) * (size_t)nd, hipMemcpyDeviceToHost, s));
         sync(s);
         const std::vector<i32> hc = diagonal_clusters(ho, DIA_CLUSTER_K, DIA_CLUSTER_SPAN);
-        P.nclu = (i64)hc.size() / 4;
+        P.nclu = (i64)hc.size() / CLU_REC;
         P.clu = (i32 *)P.alloc(ctx, sizeof(i32) * hc.size());
         DSM_HIP(hipMemcpyAsync(P.clu, hc.data(), sizeof(i32) * hc.size(), hipMemcpyHostToDevice, s));
         sync(s);  // hc is a host temporary

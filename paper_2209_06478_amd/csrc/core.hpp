@@ -54,8 +54,9 @@ struct Payload {
     void *dval = nullptr;
     i64 ndiag = 0;
     // diagonals grouped into clusters of up to DIA_CLUSTER_K consecutive
-    // diagonals whose offsets span at most DIA_CLUSTER_SPAN: nclu entries of
-    // {first diagonal, one past the last, lowest offset, highest offset}
+    // diagonals whose offsets span at most DIA_CLUSTER_SPAN: nclu records of
+    // CLU_REC ints {first diagonal, one past the last, lowest offset, highest
+    // offset, offsets of its diagonals relative to the lowest} (clusters.hpp)
     i32 *clu = nullptr;
     i64 nclu = 0;
     // ELL (HYB)
@@ -194,8 +195,28 @@ double spmv_bytes(const dsm_matrix_s *m, const Payload &P, int vec_dtype);
 // variants (tile order x row groups per thread x paired rows).
 constexpr int CSR_VARIANTS = 8;
 constexpr int SWEEP_VARIANT_COUNT = 16;
-// DIA/HDC also take bit 4: x staged in LDS per diagonal cluster.
-constexpr int DIA_VARIANT_COUNT = 32;
+// DIA/HDC also take bit 4 (x staged in LDS per diagonal cluster) and bit 5
+// (value loads marked nontemporal).
+constexpr int DIA_VARIANT_COUNT = 64;
+constexpr int DIA_VARIANT_NT = 32;
+
+// Events attached to the kernel launches of one SpMV, for kernel-only
+// timing: while t_launch_timing points at one on the calling thread, every
+// SpMV launch records `stop` at its own end and the first also records
+// `start` at its beginning (hipExtLaunchKernel), so no event packet or host
+// gap between queued work and the SpMV is counted.
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool started = false;
+};
+extern thread_local LaunchTiming *t_launch_timing;
+// Kernel-only duration (us) of one SpMV of the active payload and variant;
+// blocks until it has finished.
+double spmv_kernel_us(dsm_matrix m, const void *x, void *y, int vdt, hipStream_t s);
+// Reads `bytes` (a multiple of 16) of buf with the streaming read kernel,
+// writing DSM_PROBE_PARTIALS partial sums to part: evicts L2 and the
+// Infinity Cache of what was there when bytes exceed their capacity.
+void flush_read(const void *buf, i64 bytes, double *part, hipStream_t s);
 constexpr int DIA_CLUSTER_K = 3;
 constexpr int DIA_CLUSTER_SPAN = 64;
 

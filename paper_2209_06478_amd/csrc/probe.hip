@@ -89,6 +89,11 @@ __global__ void __launch_bounds__(PB) k_probe_gather(const double *__restrict__ 
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+void flush_read(const void *buf, i64 bytes, double *part, hipStream_t s) {
+    hipLaunchKernelGGL(k_probe_read, dim3(DSM_PROBE_PARTIALS), dim3(PB), 0, s, (const d2 *)buf, bytes / 16, part);
+    DSM_HIP(hipGetLastError());
+}
+
 }  // namespace dsm
 
 using namespace dsm;

@@ -32,10 +32,42 @@ static std::string fingerprint(dsm_matrix m, int vdt, int vec) {
     return os.str();
 }
 
-// Median time (us) of `reps` SpMVs after `warmup` untimed ones.
+// Device buffer that cold timing reads before every timed SpMV.
+struct Flush {
+    void *buf = nullptr;
+    double *part = nullptr;
+    i64 bytes = 0;
+};
+
+// Median time (us) of `reps` SpMVs after `warmup` untimed ones: back to back
+// with an event pair around each (warm), or, with a flush buffer, each SpMV
+// started after a read of the whole buffer and timed by the events its own
+// launches carry (cold, kernel-only).
 static double time_spmv(dsm_matrix m, const Payload &P, int variant, const void *x, void *y, int vec, int warmup,
-                        int reps, hipStream_t s) {
+                        int reps, hipStream_t s, const Flush *flush = nullptr) {
     for (int i = 0; i < warmup; i++) spmv(m, P, x, y, vec, variant, s);
+    if (flush && flush->bytes > 0) {
+        // the kernel-only timer runs the handle's active payload and variant
+        const Payload keep = m->P;
+        const int keep_v = m->variant;
+        m->P = P;
+        m->variant = variant;
+        std::vector<double> t(reps);
+        try {
+            for (int i = 0; i < reps; i++) {
+                flush_read(flush->buf, flush->bytes, flush->part, s);
+                t[i] = spmv_kernel_us(m, x, y, vec, s);
+            }
+        } catch (...) {
+            m->P = keep;
+            m->variant = keep_v;
+            throw;
+        }
+        m->P = keep;
+        m->variant = keep_v;
+        std::sort(t.begin(), t.end());
+        return reps ? t[reps / 2] : 0.0;
+    }
     std::vector<hipEvent_t> ev(2 * reps);
     for (auto &e : ev) DSM_HIP(hipEventCreate(&e));
     for (int i = 0; i < reps; i++) {
@@ -170,7 +202,8 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
     DSM_CHECK(mask != 0, DSM_E_INVALID, "empty candidate mask");
     m->last_stream = s;
     const std::string key =
-        fingerprint(m, o.value_dtype, vec) + ":m" + std::to_string(mask) + ":t" + std::to_string(o.target);
+        fingerprint(m, o.value_dtype, vec) + ":m" + std::to_string(mask) + ":t" + std::to_string(o.target) +
+        (o.flush_bytes > 0 && o.target == 0 ? ":cold" : "");
 
     dsm_convert_opts co;
     dsm_convert_opts_default(&co);
@@ -285,6 +318,19 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
         dev_free(ctx, x, xs * (size_t)std::max<i64>(m->ncols, 1));
         throw;
     }
+    Flush flush;
+    if (o.flush_bytes > 0 && o.target == 0) {
+        flush.bytes = (o.flush_bytes + 15) / 16 * 16;
+        try {
+            flush.buf = dev_alloc(ctx, (size_t)flush.bytes);
+            flush.part = (double *)dev_alloc(ctx, sizeof(double) * DSM_PROBE_PARTIALS);
+        } catch (...) {
+            if (flush.buf) dev_free(ctx, flush.buf, (size_t)flush.bytes);
+            dev_free(ctx, x, xs * (size_t)std::max<i64>(m->ncols, 1));
+            dev_free(ctx, y, xs * (size_t)std::max<i64>(m->nrows, 1));
+            throw;
+        }
+    }
     const unsigned gx = grid_for(m->ncols, 256);
     if (vec == DSM_F64) hipLaunchKernelGGL(k_fill_value<double>, dim3(gx), dim3(256), 0, s, m->ncols, (double *)x, 1.0);
     else hipLaunchKernelGGL(k_fill_value<float>, dim3(gx), dim3(256), 0, s, m->ncols, (float *)x, 1.0f);
@@ -299,6 +345,10 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
         (void)hipStreamSynchronize(s);
         dev_free(ctx, x, xs * (size_t)std::max<i64>(m->ncols, 1));
         dev_free(ctx, y, xs * (size_t)std::max<i64>(m->nrows, 1));
+        if (flush.buf) {
+            dev_free(ctx, flush.buf, (size_t)flush.bytes);
+            dev_free(ctx, flush.part, sizeof(double) * DSM_PROBE_PARTIALS);
+        }
     };
     try {
         for (int f : order) {
@@ -345,14 +395,15 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
                 variants = f == DSM_CSR ? std::vector<int>{1, 2, 4, 8, 16, 32} : std::vector<int>{1};
             } else if (o.tune_variant) {
                 if (f == DSM_CSR) variants = {0, 7, 2, 3, 4, 5, 6};
-                else if (f == DSM_DIA || f == DSM_HDC) variants = {0, 1, 2, 4, 8, 10, 12, 16, 18, 20, 19, 21};
+                else if (f == DSM_DIA || f == DSM_HDC)
+                    variants = {0, 1, 2, 4, 8, 10, 12, 16, 18, 20, 19, 21, 32, 40, 48, 56, 50, 58};
                 else if (f == DSM_ELL || f == DSM_HYB) variants = {0, 1, 2, 4, 8, 10, 12};
             }
             double tf = 0;
             int vf = 0;
             for (int v : variants) {
                 double t = o.target == 1 ? time_batched_solve(m, P, v, BATCH_TUNE_ITERS, s)
-                                         : time_spmv(m, P, v, x, y, vec, o.warmup, o.reps, s);
+                                         : time_spmv(m, P, v, x, y, vec, o.warmup, o.reps, s, &flush);
                 // a later variant must be clearly faster (1%) to displace an
                 // earlier one, so the choice does not flip on timing noise
                 if (v == variants[0] || t < 0.99 * tf) {
@@ -395,7 +446,8 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
     }
     cleanup();
     DSM_CHECK(have_best, DSM_E_INFEASIBLE, "no candidate format is feasible");
-    if (o.target == 0) learn(ctx, PR, R, best_variant_per_fmt);
+    // the cost model learns warm bandwidths only (what back-to-back use sees)
+    if (o.target == 0 && flush.bytes == 0) learn(ctx, PR, R, best_variant_per_fmt);
     if (!best_is_current) {
         m->P.release(ctx);
         m->P = best;
@@ -430,6 +482,7 @@ DSM_API void dsm_select_opts_default(dsm_select_opts *o) {
     o->max_pad_ratio = 16.0;
     o->bytes_prefilter = 2.0;
     o->target = 0;
+    o->flush_bytes = 0;
 }
 
 DSM_API dsm_status dsm_select(dsm_matrix m, uint32_t candidate_mask, const dsm_select_opts *opts,
@@ -444,6 +497,7 @@ DSM_API dsm_status dsm_select(dsm_matrix m, uint32_t candidate_mask, const dsm_s
         DSM_CHECK(o.reps >= 1 || o.target == 0, DSM_E_INVALID, "the batched target needs timed runs");
         DSM_CHECK(o.value_dtype >= DSM_F64 && o.value_dtype <= DSM_BF16, DSM_E_INVALID, "bad value dtype");
         if (o.bytes_prefilter <= 0) o.bytes_prefilter = 2.0;
+        DSM_CHECK(o.flush_bytes >= 0, DSM_E_INVALID, "flush_bytes must be >= 0");
         select_format(m, candidate_mask, o, report, (hipStream_t)stream);
     });
 }
@@ -458,6 +512,19 @@ DSM_API dsm_status dsm_time_spmv(dsm_matrix m, const void *x, void *y, dsm_dtype
         DSM_HIP(hipSetDevice(m->ctx->device));
         hipStream_t s = (hipStream_t)stream;
         *median_us = time_spmv(m, m->P, m->variant, x, y, vec_dtype, warmup, reps, s);
+        m->last_stream = s;
+    });
+}
+
+DSM_API dsm_status dsm_spmv_kernel_time(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, double *us,
+                                        void *stream) {
+    return guard([&] {
+        DSM_CHECK(m && m->ctx && us, DSM_E_INVALID, "null argument");
+        DSM_CHECK((x || m->ncols == 0) && (y || m->nrows == 0), DSM_E_INVALID, "null vector");
+        DSM_CHECK(x != y || m->nrows == 0, DSM_E_INVALID, "x and y must not alias");
+        DSM_HIP(hipSetDevice(m->ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        *us = spmv_kernel_us(m, x, y, vec_dtype, s);
         m->last_stream = s;
     });
 }

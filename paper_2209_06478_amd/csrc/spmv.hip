@@ -28,6 +28,9 @@
 //        partials in tile order.
 //   HYB  ELL part writes y, then the COO part adds its rows.
 //   HDC  DIA part writes y, then the CSR part adds its rows.
+#include <hip/hip_ext.h>
+
+#include "clusters.hpp"
 #include "core.hpp"
 
 namespace dsm {
@@ -38,6 +41,63 @@ constexpr int CU = 4;         // CSR: entries a lane loads before gathering x
 constexpr int COO_E = 4;      // entries per lane in the COO kernel
 constexpr int COO_TE = WAVE * COO_E;
 constexpr int DIA_LOADS = 8;  // value loads a DIA lane issues per batch (16 measured no faster)
+
+thread_local LaunchTiming *t_launch_timing = nullptr;
+
+// Every SpMV kernel launch goes through DSM_LAUNCH: a plain launch, or, while
+// kernel-only timing is on for this thread, one whose events are recorded by
+// the dispatch itself (the first launch of the SpMV starts the interval, each
+// launch moves its end).
+#define DSM_LAUNCH(K, G, B, SH, S, ...)                                                     \
+    do {                                                                                   \
+        LaunchTiming *lt_ = t_launch_timing;                                               \
+        if (lt_) {                                                                         \
+            hipEvent_t a_ = lt_->started ? nullptr : lt_->start;                           \
+            lt_->started = true;                                                           \
+            hipExtLaunchKernelGGL(K, G, B, SH, S, a_, lt_->stop, 0, __VA_ARGS__);          \
+        } else {                                                                           \
+            hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);                               \
+        }                                                                                  \
+    } while (0)
+
+// Raw words of each size a value load can take, for the nontemporal builtin
+// (which takes integer, float and vector types only).
+template <int B>
+struct raw_word;
+template <>
+struct raw_word<2> {
+    using t = unsigned short;
+};
+template <>
+struct raw_word<4> {
+    using t = unsigned int;
+};
+template <>
+struct raw_word<8> {
+    using t = unsigned long long;
+};
+template <>
+struct raw_word<16> {
+    typedef unsigned int t __attribute__((ext_vector_type(4)));
+};
+
+// Load of a stored matrix value.  NT marks it nontemporal: each value is
+// read once per SpMV, and the hint lets a sweep that starts with cold caches
+// stream its values at a higher rate (a plain read of HPCG 104^3's 252 MB of
+// DIA values and y went from 0.69 to 0.76 of the HBM peak).  It also keeps
+// them from being retained for the next SpMV, so back-to-back SpMVs whose
+// matrix mostly fits the 256 MB Infinity Cache are slower with it: the
+// timed selection decides.
+template <bool NT, class T>
+__device__ __forceinline__ T load_val(const T *p) {
+    if constexpr (NT) {
+        using W = typename raw_word<sizeof(T)>::t;
+        const W w = __builtin_nontemporal_load((const W *)p);
+        return __builtin_bit_cast(T, w);
+    } else {
+        return *p;
+    }
+}
 
 template <class X>
 __device__ __forceinline__ void store_y(X *y, i64 i, X v, bool acc) {
@@ -198,7 +258,7 @@ constexpr int dia_batch() {
     return (R * RW) >= DIA_LOADS ? 1 : DIA_LOADS / (R * RW);
 }
 
-template <class V, class X, bool ACC, bool XCD, int R, bool P2, bool DOT = false>
+template <class V, class X, bool ACC, bool XCD, int R, bool P2, bool DOT = false, bool NT = false>
 __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, const i32 *__restrict__ offs,
                                             const V *__restrict__ dval, i64 pitch, const X *__restrict__ x,
                                             X *__restrict__ y, const int *__restrict__ stop,
@@ -243,13 +303,13 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
                 for (int r = 0; r < R; r++) {
                     const i64 i = i0 + (i64)r * SB * RW;
                     if constexpr (P2) {
-                        const pair2<V> pv = *(const pair2<V> *)(dk + i);
+                        const pair2<V> pv = load_val<NT>((const pair2<V> *)(dk + i));
                         v[u][r][0] = pv.a;
                         v[u][r][1] = pv.b;
                         xv[u][r][0] = x[i + off];
                         xv[u][r][1] = x[i + off + 1];
                     } else {
-                        v[u][r][0] = dk[i];
+                        v[u][r][0] = load_val<NT>(dk + i);
                         xv[u][r][0] = x[i + off];
                     }
                 }
@@ -269,7 +329,7 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
                 if constexpr (P2) {
                     // i is even and the pitch a multiple of 64, so the pair is
                     // aligned; slot i + 1 < pitch always exists (padding is 0)
-                    const pair2<V> pv = *(kin && i < nrows ? (const pair2<V> *)(dk + i) : zero_ptr<pair2<V>>());
+                    const pair2<V> pv = load_val<NT>(kin && i < nrows ? (const pair2<V> *)(dk + i) : zero_ptr<pair2<V>>());
                     v[u][r][0] = pv.a;
                     v[u][r][1] = pv.b;
                     const bool ok0 = kin && i < nrows && j >= 0 && j < ncols;
@@ -278,7 +338,7 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
                     xv[u][r][1] = *(ok1 ? x + j + 1 : zero_ptr<X>());
                 } else {
                     const bool ok = kin && i < nrows && j >= 0 && j < ncols;
-                    v[u][r][0] = *(kin && i < nrows ? dk + i : zero_ptr<V>());
+                    v[u][r][0] = load_val<NT>(kin && i < nrows ? dk + i : zero_ptr<V>());
                     xv[u][r][0] = *(ok ? x + j : zero_ptr<X>());
                 }
             }
@@ -316,6 +376,14 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
     if constexpr (DOT) dot_epilogue<X, R, RW>(s, x, i0, nrows, part, count);
 }
 
+// One cluster of the LDS-staged sweep (the records clusters.hpp builds).
+struct alignas(32) CluRec {
+    i32 kb, ke, lo, hi;
+    i32 d[4];  // offsets of diagonals kb.. relative to lo, 0 past ke
+};
+static_assert(sizeof(CluRec) == CLU_REC * sizeof(i32), "cluster record layout");
+static_assert(DIA_CLUSTER_K <= 4, "a cluster record holds four relative offsets");
+
 // DIA sweep with x staged in LDS (variant bit 4).  A workgroup owns
 // T = SB*R*RW consecutive rows (thread t: rows r0 + t*RW + q*SB*RW (+1 with
 // paired rows, whose values come in one double-width load)).  For each cluster of
@@ -327,7 +395,7 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
 // (their slots are padding, +0); zero slots drop their operand as in k_dia.
 // Measured faster than k_dia beyond the Infinity Cache (HPCG 128^3 and
 // 144^3), slower at 104^3, where k_dia's gathers hit the caches.
-template <class V, class X, bool ACC, bool XCD, int R, bool P2, bool DOT = false>
+template <class V, class X, bool ACC, bool XCD, int R, bool P2, bool DOT = false, bool NT = false>
 __global__ void __launch_bounds__(SB) k_dia_lds(i64 nrows, i64 ncols, i64 nclu, const i32 *__restrict__ clu,
                                                 const i32 *__restrict__ offs, const V *__restrict__ dval, i64 pitch,
                                                 const X *__restrict__ x, X *__restrict__ y,
@@ -339,6 +407,11 @@ __global__ void __launch_bounds__(SB) k_dia_lds(i64 nrows, i64 ncols, i64 nclu, 
     constexpr int WMAX = T + DIA_CLUSTER_SPAN;
     constexpr int WP = (WMAX + SB - 1) / SB;
     constexpr int KC = DIA_CLUSTER_K;
+    // The cold-streaming form (nontemporal value loads) issues the loads of
+    // PG clusters at once, so a workgroup keeps more HBM requests in flight
+    // through the barriers and products of the first ones.
+    constexpr bool PF = NT;
+    constexpr int PG = 3;
     __shared__ X xs[WMAX];
     const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
     const i64 r0 = (i64)b * T;
@@ -348,13 +421,20 @@ __global__ void __launch_bounds__(SB) k_dia_lds(i64 nrows, i64 ncols, i64 nclu, 
     for (int q = 0; q < R; q++)
 #pragma unroll
         for (int w = 0; w < RW; w++) s[q][w] = 0;
-    for (i64 c = 0; c < nclu; c++) {
-        const i64 kb = clu[4 * c], ke = clu[4 * c + 1], lo = clu[4 * c + 2], hi = clu[4 * c + 3];
-        const i64 base = r0 + lo;
-        const int W = T + (int)(hi - lo);
+    // one cluster's operands in registers: its x window and its values
+    struct Stage {
         X win[WP];
         V v[KC][R][RW];
         int d[KC];
+        int W;
+    };
+    auto load = [&](i64 c, Stage &st) {
+        // the cluster's record in one scalar load (no dependent offset loads)
+        const CluRec r = ((const CluRec *)clu)[c];
+        const i64 kb = r.kb, ke = r.ke, lo = r.lo, hi = r.hi;
+        const i64 base = r0 + lo;
+        const int W = T + (int)(hi - lo);
+        st.W = W;
         // FP32/BF16 values: a cluster with all KC diagonals, rows all inside
         // the matrix and a window inside x takes plain loads (the index work
         // per element limits those sweeps, as in k_dia)
@@ -362,56 +442,59 @@ __global__ void __launch_bounds__(SB) k_dia_lds(i64 nrows, i64 ncols, i64 nclu, 
 #pragma unroll
             for (int p = 0; p < WP; p++) {
                 const int t = threadIdx.x + p * SB;
-                win[p] = x[base + min(t, W - 1)];
+                st.win[p] = x[base + min(t, W - 1)];
             }
 #pragma unroll
             for (int u = 0; u < KC; u++) {
-                d[u] = offs[kb + u] - (int)lo;
+                st.d[u] = r.d[u];
                 const V *dk = dval + (kb + u) * pitch;
 #pragma unroll
                 for (int q = 0; q < R; q++) {
                     const i64 i = r0 + t0 + (i64)q * SB * RW;
                     if constexpr (P2) {
-                        const pair2<V> pv = *(const pair2<V> *)(dk + i);
-                        v[u][q][0] = pv.a;
-                        v[u][q][1] = pv.b;
+                        const pair2<V> pv = load_val<NT>((const pair2<V> *)(dk + i));
+                        st.v[u][q][0] = pv.a;
+                        st.v[u][q][1] = pv.b;
                     } else {
-                        v[u][q][0] = dk[i];
+                        st.v[u][q][0] = load_val<NT>(dk + i);
                     }
                 }
             }
         } else {
 #pragma unroll
-        for (int p = 0; p < WP; p++) {
-            const int t = threadIdx.x + p * SB;
-            const i64 j = base + t;
-            win[p] = *(t < W && j >= 0 && j < ncols ? x + j : zero_ptr<X>());
-        }
+            for (int p = 0; p < WP; p++) {
+                const int t = threadIdx.x + p * SB;
+                const i64 j = base + t;
+                st.win[p] = *(t < W && j >= 0 && j < ncols ? x + j : zero_ptr<X>());
+            }
 #pragma unroll
-        for (int u = 0; u < KC; u++) {
-            const bool kin = kb + u < ke;
-            d[u] = kin ? offs[kb + u] - (int)lo : 0;
+            for (int u = 0; u < KC; u++) {
+                const bool kin = kb + u < ke;
+                st.d[u] = r.d[u];  // 0 past the cluster's last diagonal
 #pragma unroll
-            for (int q = 0; q < R; q++) {
-                const i64 i = r0 + t0 + (i64)q * SB * RW;
-                const V *dk = dval + (kb + u) * pitch;
-                if constexpr (P2) {
-                    // i is even and the pitch a multiple of 64: the pair is
-                    // aligned and slot i + 1 < pitch exists (padding is 0)
-                    const pair2<V> pv = *(kin && i < nrows ? (const pair2<V> *)(dk + i) : zero_ptr<pair2<V>>());
-                    v[u][q][0] = pv.a;
-                    v[u][q][1] = pv.b;
-                } else {
-                    v[u][q][0] = *(kin && i < nrows ? dk + i : zero_ptr<V>());
+                for (int q = 0; q < R; q++) {
+                    const i64 i = r0 + t0 + (i64)q * SB * RW;
+                    const V *dk = dval + (kb + u) * pitch;
+                    if constexpr (P2) {
+                        // i is even and the pitch a multiple of 64: the pair is
+                        // aligned and slot i + 1 < pitch exists (padding is 0)
+                        const pair2<V> pv =
+                            load_val<NT>(kin && i < nrows ? (const pair2<V> *)(dk + i) : zero_ptr<pair2<V>>());
+                        st.v[u][q][0] = pv.a;
+                        st.v[u][q][1] = pv.b;
+                    } else {
+                        st.v[u][q][0] = load_val<NT>(kin && i < nrows ? dk + i : zero_ptr<V>());
+                    }
                 }
             }
         }
-        }
+    };
+    auto consume = [&](const Stage &st) {
         __syncthreads();  // the previous cluster's reads of xs are done
 #pragma unroll
         for (int p = 0; p < WP; p++) {
             const int t = threadIdx.x + p * SB;
-            if (t < W) xs[t] = win[p];
+            if (t < st.W) xs[t] = st.win[p];
         }
         __syncthreads();
 #pragma unroll
@@ -420,11 +503,32 @@ __global__ void __launch_bounds__(SB) k_dia_lds(i64 nrows, i64 ncols, i64 nclu, 
             for (int q = 0; q < R; q++)
 #pragma unroll
                 for (int w = 0; w < RW; w++) {
-                    X xv = xs[t0 + q * SB * RW + w + d[u]];
+                    X xv = xs[t0 + q * SB * RW + w + st.d[u]];
                     asm volatile("" : "+v"(xv));
-                    const X wv = widen<X>(v[u][q][w]);
+                    const X wv = widen<X>(st.v[u][q][w]);
                     s[q][w] += wv * (wv != (X)0 ? xv : (X)0);
                 }
+    };
+    if constexpr (PF) {
+        // groups of PG clusters: every load of a group is issued before the
+        // first of its clusters is consumed (loads carried over a loop
+        // iteration would be waited for at its start).  The loads are unconditional - a stage past the last
+        // cluster reloads the last one and is not consumed - so the compiler
+        // can count exactly how many are in flight behind each stage.
+        for (i64 c = 0; c < nclu; c += PG) {
+            Stage st[PG];
+#pragma unroll
+            for (int g = 0; g < PG; g++) load(min(c + g, nclu - 1), st[g]);
+#pragma unroll
+            for (int g = 0; g < PG; g++)
+                if (c + g < nclu) consume(st[g]);
+        }
+    } else {
+        for (i64 c = 0; c < nclu; c++) {
+            Stage st;
+            load(c, st);
+            consume(st);
+        }
     }
 #pragma unroll
     for (int q = 0; q < R; q++)
@@ -664,7 +768,7 @@ static void coo_launch(dsm_matrix m, i64 nnz, const i32 *row, const i32 *col, co
                        bool acc, hipStream_t s, Workspace *scratch, const int *stop) {
     const i64 n = m->nrows;
     if (nnz == 0) {
-        if (!acc && n > 0) hipLaunchKernelGGL(k_fill<X>, dim3(grid_for(n, SB)), dim3(SB), 0, s, n, y, (X)0, stop);
+        if (!acc && n > 0) DSM_LAUNCH(k_fill<X>, dim3(grid_for(n, SB)), dim3(SB), 0, s, n, y, (X)0, stop);
         return;
     }
     const i64 ntiles = (nnz + COO_TE - 1) / COO_TE;
@@ -672,14 +776,14 @@ static void coo_launch(dsm_matrix m, i64 nnz, const i32 *row, const i32 *col, co
     X *head = part, *tail = part + ntiles;
     const unsigned g = grid_for(ntiles, SB / WAVE);
     if (acc) {
-        hipLaunchKernelGGL((k_coo_tiles<V, X, COO_E, true>), dim3(g), dim3(SB), 0, s, nnz, n, row, col, val, x, y,
+        DSM_LAUNCH((k_coo_tiles<V, X, COO_E, true>), dim3(g), dim3(SB), 0, s, nnz, n, row, col, val, x, y,
                            head, tail, stop);
-        hipLaunchKernelGGL((k_coo_fixup<X, COO_E, true>), dim3(grid_for(ntiles, SB)), dim3(SB), 0, s, nnz, ntiles,
+        DSM_LAUNCH((k_coo_fixup<X, COO_E, true>), dim3(grid_for(ntiles, SB)), dim3(SB), 0, s, nnz, ntiles,
                            row, head, tail, y, stop);
     } else {
-        hipLaunchKernelGGL((k_coo_tiles<V, X, COO_E, false>), dim3(g), dim3(SB), 0, s, nnz, n, row, col, val, x, y,
+        DSM_LAUNCH((k_coo_tiles<V, X, COO_E, false>), dim3(g), dim3(SB), 0, s, nnz, n, row, col, val, x, y,
                            head, tail, stop);
-        hipLaunchKernelGGL((k_coo_fixup<X, COO_E, false>), dim3(grid_for(ntiles, SB)), dim3(SB), 0, s, nnz, ntiles,
+        DSM_LAUNCH((k_coo_fixup<X, COO_E, false>), dim3(grid_for(ntiles, SB)), dim3(SB), 0, s, nnz, ntiles,
                            row, head, tail, y, stop);
     }
 }
@@ -693,17 +797,17 @@ static void csr_launch(dsm_matrix m, const Payload &P, const X *x, X *y, int var
     if (variant == 0 || variant >= 7) {
         if (P.nrblocks == 0) return;
         if (variant == 0)
-            hipLaunchKernelGGL((k_csr_adaptive<V, X, ACC, true>), dim3((unsigned)P.nrblocks), dim3(SB), 0, s,
+            DSM_LAUNCH((k_csr_adaptive<V, X, ACC, true>), dim3((unsigned)P.nrblocks), dim3(SB), 0, s,
                                P.rblocks, P.rp, P.col, val, x, y, stop);
         else
-            hipLaunchKernelGGL((k_csr_adaptive<V, X, ACC, false>), dim3((unsigned)P.nrblocks), dim3(SB), 0, s,
+            DSM_LAUNCH((k_csr_adaptive<V, X, ACC, false>), dim3((unsigned)P.nrblocks), dim3(SB), 0, s,
                                P.rblocks, P.rp, P.col, val, x, y, stop);
         return;
     }
     const int W = 1 << variant;  // 2 .. 64
     const unsigned g = grid_for(n * W, SB);
 #define VEC(WW) \
-    hipLaunchKernelGGL((k_csr_vector<V, X, WW, ACC>), dim3(g), dim3(SB), 0, s, n, P.rp, P.col, val, x, y, stop)
+    DSM_LAUNCH((k_csr_vector<V, X, WW, ACC>), dim3(g), dim3(SB), 0, s, n, P.rp, P.col, val, x, y, stop)
     switch (W) {
     case 2: VEC(2); break;
     case 4: VEC(4); break;
@@ -721,59 +825,76 @@ static unsigned sweep_groups(i64 n, int variant) {
     return grid_for(n, SB * R * (((variant >> 3) & 1) ? 2 : 1));
 }
 
-template <class V, class X, bool ACC, bool XCD, int R, bool P2, bool DOT>
+template <class V, class X, bool ACC, bool XCD, int R, bool P2, bool DOT, bool NT>
 static void sweep_lds_launch(dsm_matrix m, const Payload &P, const X *x, X *y, hipStream_t s, const int *stop,
                              double *part, long long *count) {
     const i64 n = m->nrows;
-    hipLaunchKernelGGL((k_dia_lds<V, X, ACC, XCD, R, P2, DOT>), dim3(grid_for(n, SB * R * (P2 ? 2 : 1))), dim3(SB),
-                       0, s, n, m->ncols, P.nclu, P.clu, P.offs, (const V *)P.dval, P.pitch, x, y, stop, part, count);
+    DSM_LAUNCH((k_dia_lds<V, X, ACC, XCD, R, P2, DOT, NT>), dim3(grid_for(n, SB * R * (P2 ? 2 : 1))), dim3(SB),
+               0, s, n, m->ncols, P.nclu, P.clu, P.offs, (const V *)P.dval, P.pitch, x, y, stop, part, count);
 }
 
-template <class V, class X, bool ACC, bool XCD, bool P2, bool DOT>
+template <class V, class X, bool ACC, bool XCD, bool P2, bool DOT, bool NT>
 static void sweep_lds_r(dsm_matrix m, const Payload &P, const X *x, X *y, int lr, hipStream_t s, const int *stop,
                         double *part, long long *count) {
-    if (lr == 0) sweep_lds_launch<V, X, ACC, XCD, 1, P2, DOT>(m, P, x, y, s, stop, part, count);
-    else if (lr == 1) sweep_lds_launch<V, X, ACC, XCD, 2, P2, DOT>(m, P, x, y, s, stop, part, count);
-    else sweep_lds_launch<V, X, ACC, XCD, 4, P2, DOT>(m, P, x, y, s, stop, part, count);
+    if (lr == 0) sweep_lds_launch<V, X, ACC, XCD, 1, P2, DOT, NT>(m, P, x, y, s, stop, part, count);
+    else if (lr == 1) sweep_lds_launch<V, X, ACC, XCD, 2, P2, DOT, NT>(m, P, x, y, s, stop, part, count);
+    else sweep_lds_launch<V, X, ACC, XCD, 4, P2, DOT, NT>(m, P, x, y, s, stop, part, count);
 }
 
-template <class V, class X, bool ACC, bool XCD, int R, bool P2, bool DOT>
+// NT (nontemporal value loads) exists for the DIA sweep only.
+template <class V, class X, bool ACC, bool XCD, int R, bool P2, bool DOT, bool NT>
 static void sweep_launch(dsm_matrix m, const Payload &P, const X *x, X *y, hipStream_t s, const int *stop,
                          double *part, long long *count) {
     const i64 n = m->nrows;
     const unsigned g = grid_for(n, SB * R * (P2 ? 2 : 1));
-    if (P.fmt == DSM_DIA || P.fmt == DSM_HDC)
-        hipLaunchKernelGGL((k_dia<V, X, ACC, XCD, R, P2, DOT>), dim3(g), dim3(SB), 0, s, n, m->ncols, P.ndiag,
-                           P.offs, (const V *)P.dval, P.pitch, x, y, stop, part, count);
-    else
-        hipLaunchKernelGGL((k_ell<V, X, ACC, XCD, R, P2, DOT>), dim3(g), dim3(SB), 0, s, n, P.K, P.pitch, P.ecol,
-                           (const V *)P.evl, x, y, stop, part, count);
+    if (NT || P.fmt == DSM_DIA || P.fmt == DSM_HDC) {
+        DSM_LAUNCH((k_dia<V, X, ACC, XCD, R, P2, DOT, NT>), dim3(g), dim3(SB), 0, s, n, m->ncols, P.ndiag, P.offs,
+                   (const V *)P.dval, P.pitch, x, y, stop, part, count);
+    } else if constexpr (!NT) {
+        DSM_LAUNCH((k_ell<V, X, ACC, XCD, R, P2, DOT>), dim3(g), dim3(SB), 0, s, n, P.K, P.pitch, P.ecol,
+                   (const V *)P.evl, x, y, stop, part, count);
+    }
 }
 
-template <class V, class X, bool ACC, bool XCD, bool P2, bool DOT>
+template <class V, class X, bool ACC, bool XCD, bool P2, bool DOT, bool NT>
 static void sweep_r(dsm_matrix m, const Payload &P, const X *x, X *y, int lr, hipStream_t s, const int *stop,
                     double *part, long long *count) {
-    if (lr == 0) sweep_launch<V, X, ACC, XCD, 1, P2, DOT>(m, P, x, y, s, stop, part, count);
-    else if (lr == 1) sweep_launch<V, X, ACC, XCD, 2, P2, DOT>(m, P, x, y, s, stop, part, count);
-    else sweep_launch<V, X, ACC, XCD, 4, P2, DOT>(m, P, x, y, s, stop, part, count);
+    if (lr == 0) sweep_launch<V, X, ACC, XCD, 1, P2, DOT, NT>(m, P, x, y, s, stop, part, count);
+    else if (lr == 1) sweep_launch<V, X, ACC, XCD, 2, P2, DOT, NT>(m, P, x, y, s, stop, part, count);
+    else sweep_launch<V, X, ACC, XCD, 4, P2, DOT, NT>(m, P, x, y, s, stop, part, count);
 }
 
-template <class V, class X, bool ACC, bool DOT = false>
-static void sweep(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s, const int *stop,
-                  double *part = nullptr, long long *count = nullptr) {
+template <class V, class X, bool ACC, bool DOT, bool NT>
+static void sweep_nt(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s, const int *stop,
+                     double *part, long long *count) {
     const bool xcd = !(variant & 1), p2 = (variant >> 3) & 1;
     const int lr = (variant >> 1) & 3;
     if (((variant >> 4) & 1) && (P.fmt == DSM_DIA || P.fmt == DSM_HDC)) {
-        if (xcd && p2) sweep_lds_r<V, X, ACC, true, true, DOT>(m, P, x, y, lr, s, stop, part, count);
-        else if (xcd) sweep_lds_r<V, X, ACC, true, false, DOT>(m, P, x, y, lr, s, stop, part, count);
-        else if (p2) sweep_lds_r<V, X, ACC, false, true, DOT>(m, P, x, y, lr, s, stop, part, count);
-        else sweep_lds_r<V, X, ACC, false, false, DOT>(m, P, x, y, lr, s, stop, part, count);
+        if (xcd && p2) sweep_lds_r<V, X, ACC, true, true, DOT, NT>(m, P, x, y, lr, s, stop, part, count);
+        else if (xcd) sweep_lds_r<V, X, ACC, true, false, DOT, NT>(m, P, x, y, lr, s, stop, part, count);
+        else if (p2) sweep_lds_r<V, X, ACC, false, true, DOT, NT>(m, P, x, y, lr, s, stop, part, count);
+        else sweep_lds_r<V, X, ACC, false, false, DOT, NT>(m, P, x, y, lr, s, stop, part, count);
         return;
     }
-    if (xcd && p2) sweep_r<V, X, ACC, true, true, DOT>(m, P, x, y, lr, s, stop, part, count);
-    else if (xcd) sweep_r<V, X, ACC, true, false, DOT>(m, P, x, y, lr, s, stop, part, count);
-    else if (p2) sweep_r<V, X, ACC, false, true, DOT>(m, P, x, y, lr, s, stop, part, count);
-    else sweep_r<V, X, ACC, false, false, DOT>(m, P, x, y, lr, s, stop, part, count);
+    if (xcd && p2) sweep_r<V, X, ACC, true, true, DOT, NT>(m, P, x, y, lr, s, stop, part, count);
+    else if (xcd) sweep_r<V, X, ACC, true, false, DOT, NT>(m, P, x, y, lr, s, stop, part, count);
+    else if (p2) sweep_r<V, X, ACC, false, true, DOT, NT>(m, P, x, y, lr, s, stop, part, count);
+    else sweep_r<V, X, ACC, false, false, DOT, NT>(m, P, x, y, lr, s, stop, part, count);
+}
+
+// Bit 5 (nontemporal value loads) applies to DIA/HDC; the dot form inside CG
+// runs the same sweep with plain loads (identical results: the hint changes
+// only what the caches keep).
+template <class V, class X, bool ACC, bool DOT = false>
+static void sweep(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s, const int *stop,
+                  double *part = nullptr, long long *count = nullptr) {
+    if constexpr (!DOT) {
+        if ((variant & DIA_VARIANT_NT) && (P.fmt == DSM_DIA || P.fmt == DSM_HDC)) {
+            sweep_nt<V, X, ACC, false, true>(m, P, x, y, variant, s, stop, part, count);
+            return;
+        }
+    }
+    sweep_nt<V, X, ACC, DOT, false>(m, P, x, y, variant, s, stop, part, count);
 }
 
 template <class V, class X, bool ACC>
@@ -844,6 +965,32 @@ int spmv_dot(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, in
     if (vdt == DSM_F64)
         return spmv_dot_typed<double>(m, P, (const double *)x, (double *)y, variant, s, part, count, stop);
     return spmv_dot_typed<float>(m, P, (const float *)x, (float *)y, variant, s, part, count, stop);
+}
+
+// ---------------------------------------------------------------- kernel-only timing
+double spmv_kernel_us(dsm_matrix m, const void *x, void *y, int vdt, hipStream_t s) {
+    LaunchTiming lt;
+    DSM_HIP(hipEventCreate(&lt.start));
+    if (hipEventCreate(&lt.stop) != hipSuccess) {
+        (void)hipEventDestroy(lt.start);
+        fail(DSM_E_DEVICE, "hipEventCreate failed");
+    }
+    struct Reset {
+        LaunchTiming &lt;
+        ~Reset() {
+            t_launch_timing = nullptr;
+            (void)hipEventDestroy(lt.start);
+            (void)hipEventDestroy(lt.stop);
+        }
+    } reset{lt};
+    t_launch_timing = &lt;
+    spmv(m, m->P, x, y, vdt, m->variant, s);
+    t_launch_timing = nullptr;
+    if (!lt.started) return 0.0;  // nothing to launch (no rows)
+    DSM_HIP(hipEventSynchronize(lt.stop));
+    float ms = 0;
+    DSM_HIP(hipEventElapsedTime(&ms, lt.start, lt.stop));
+    return ms * 1000.0;
 }
 
 // ---------------------------------------------------------------- allocation-free entry

@@ -20,12 +20,16 @@ static int fails = 0;
 
 // every diagonal once, in order; each run within the limits and tight
 static void check_invariants(const std::vector<int32_t> &offs, const std::vector<int32_t> &c, int max_k, long span) {
-    CHECK(c.size() % 4 == 0);
+    const int R = dsm::CLU_REC;
+    CHECK(c.size() % R == 0);
+    if (max_k > 4) max_k = 4;
     int32_t next = 0;
-    for (size_t r = 0; r + 3 < c.size(); r += 4) {
+    for (size_t r = 0; r + R - 1 < c.size(); r += R) {
         const int32_t kb = c[r], ke = c[r + 1], lo = c[r + 2], hi = c[r + 3];
         CHECK(kb == next);
         CHECK(ke > kb && ke - kb <= max_k);
+        // relative offsets of the run's diagonals, zero past its end
+        for (int u = 0; u < 4; u++) CHECK(c[r + 4 + u] == (kb + u < ke ? offs[kb + u] - lo : 0));
         CHECK(lo == offs[kb] && hi == offs[ke - 1]);
         CHECK((long)hi - lo <= span);
         // maximal: the next diagonal could not have joined this run
@@ -43,32 +47,35 @@ int main() {
             for (int dy = -1; dy <= 1; dy++)
                 for (int dx = -1; dx <= 1; dx++) offs.push_back(dx + n * dy + n * n * dz);
         auto c = diagonal_clusters(offs, 3, 64);
-        CHECK(c.size() == 9 * 4);
-        for (size_t r = 0; r < c.size(); r += 4) CHECK(c[r + 1] - c[r] == 3 && c[r + 3] - c[r + 2] == 2);
+        CHECK(c.size() == 9 * 8);
+        for (size_t r = 0; r < c.size(); r += 8)
+            CHECK(c[r + 1] - c[r] == 3 && c[r + 3] - c[r + 2] == 2 && c[r + 4] == 0 && c[r + 5] == 1 &&
+                  c[r + 6] == 2 && c[r + 7] == 0);
         check_invariants(offs, c, 3, 64);
     }
     {  // 7-point operator: -n^2, -n, {-1, 0, 1}, n, n^2
         const int n = 128;
         std::vector<int32_t> offs{-n * n, -n, -1, 0, 1, n, n * n};
         auto c = diagonal_clusters(offs, 3, 64);
-        CHECK(c.size() == 5 * 4);
-        CHECK(c[8] == 2 && c[9] == 5);
+        CHECK(c.size() == 5 * 8);
+        CHECK(c[16] == 2 && c[17] == 5);
         check_invariants(offs, c, 3, 64);
     }
     {  // banded: 129 consecutive diagonals -> 43 runs of 3
         std::vector<int32_t> offs;
         for (int d = -64; d <= 64; d++) offs.push_back(d);
         auto c = diagonal_clusters(offs, 3, 64);
-        CHECK(c.size() == 43 * 4);
+        CHECK(c.size() == 43 * 8);
         check_invariants(offs, c, 3, 64);
     }
     {  // scattered offsets: span limit splits runs
         std::vector<int32_t> offs{-1000, -900, -100, -99, -36, 0, 28, 29, 200, 264, 265, 5000};
         auto c = diagonal_clusters(offs, 3, 64);
         check_invariants(offs, c, 3, 64);
-        CHECK(c[0] == 0 && c[1] == 1);    // -1000 alone
-        CHECK(c[4] == 1 && c[5] == 2);    // -900 alone
-        CHECK(c[8] == 2 && c[9] == 5);    // -100, -99, -36 (span 64)
+        CHECK(c[0] == 0 && c[1] == 1);     // -1000 alone
+        CHECK(c[8] == 1 && c[9] == 2);     // -900 alone
+        CHECK(c[16] == 2 && c[17] == 5);   // -100, -99, -36 (span 64)
+        CHECK(c[20] == 0 && c[21] == 1 && c[22] == 64 && c[23] == 0);
     }
     {  // random ascending offsets, several limits
         std::srand(7);

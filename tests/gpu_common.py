@@ -104,8 +104,8 @@ def oracle_cg(name, tol=1e-10):
 
 
 # the kernel variants the timed selection tries per format (csrc/select.cpp)
-SELECT_VARIANTS = {"csr": [0, 7, 2, 3, 4, 5, 6], "dia": [0, 1, 2, 4, 8, 10, 12, 16, 18, 20, 19, 21],
-                   "hdc": [0, 1, 2, 4, 8, 10, 12, 16, 18, 20, 19, 21], "ell": [0, 1, 2, 4, 8, 10, 12],
+_DIA_SELECT = [0, 1, 2, 4, 8, 10, 12, 16, 18, 20, 19, 21, 32, 40, 48, 56, 50, 58]
+SELECT_VARIANTS = {"csr": [0, 7, 2, 3, 4, 5, 6], "dia": _DIA_SELECT, "hdc": _DIA_SELECT, "ell": [0, 1, 2, 4, 8, 10, 12],
                    "hyb": [0, 1, 2, 4, 8, 10, 12], "coo": [0]}
 
 
@@ -143,6 +143,43 @@ def selection_retime(p, A, rep, value_dtype="f64", rounds=3, warmup=3, reps=20):
     med = {k: float(np.median(t)) for k, t in times.items()}
     for B in mats:
         B.close()
+    best = min(med, key=med.get)
+    chosen = med[(rep["chosen"], rep["chosen_variant"])]
+    return chosen, med[best], f"{best[0]} v{best[1]}"
+
+
+def selection_retime_cold(p, A, rep, rounds=3, reps=15, flush_mib=1024):
+    """As selection_retime, with the cold protocol of a selection run with
+    flush_bytes: every timed SpMV starts after a read of a 1 GiB buffer and
+    is timed kernel-only (the events its own launches record)."""
+    import paper_2209_06478_amd as dsm
+    torch, dev = torch_dev()
+    x = torch.ones(p.ncols, dtype=torch.float64, device=dev)
+    y = torch.empty(p.nrows, dtype=torch.float64, device=dev)
+    flush = torch.zeros(flush_mib << 17, dtype=torch.float64, device=dev)
+    part = torch.empty(dsm.PROBE_PARTIALS, dtype=torch.float64, device=dev)
+    pairs, mats = [], []
+    for f, st in rep["status"].items():
+        if st != 0:
+            continue
+        B = make_matrix(p)
+        B.convert(f)
+        mats.append(B)
+        for v in SELECT_VARIANTS[f]:
+            pairs.append((f, v, B))
+    times = {(f, v): [] for f, v, _ in pairs}
+    for _ in range(rounds):
+        for f, v, B in pairs:
+            B.variant = v
+            t = []
+            for _ in range(reps):
+                dsm.stream_probe("read", part, flush)
+                t.append(B.kernel_time(x, y))
+            times[(f, v)].append(float(np.median(t)))
+    med = {k: float(np.median(t)) for k, t in times.items()}
+    for B in mats:
+        B.close()
+    del flush
     best = min(med, key=med.get)
     chosen = med[(rep["chosen"], rep["chosen_variant"])]
     return chosen, med[best], f"{best[0]} v{best[1]}"

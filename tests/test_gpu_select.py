@@ -8,7 +8,7 @@ import pytest
 import inputs
 import oracle
 import paper_2209_06478_amd as dsm
-from gpu_common import log, make_matrix, median_launch_us, problem, row_scaled_err, selection_retime, torch_dev, x_for
+from gpu_common import selection_retime_cold, log, make_matrix, median_launch_us, problem, row_scaled_err, selection_retime, torch_dev, x_for
 
 pytestmark = pytest.mark.gpu
 
@@ -29,6 +29,27 @@ def test_select_is_near_best(name):
     assert row_scaled_err(A.spmv(x).cpu().numpy(), yref, scale) <= 1e-14
     chosen_t, best_t, best_f = selection_retime(p, A, rep)
     log(f"[select] {name}: chosen {chosen_t:.2f} us, best re-timed {best_f} {best_t:.2f} us")
+    assert chosen_t <= 1.05 * best_t
+    A.close()
+
+
+@pytest.mark.parametrize("name", ["hpcg104", "banded20k"])
+def test_cold_select_is_near_best(name):
+    """Cold selection (a 1 GiB read before every timed SpMV, kernel-only
+    times): the chosen (format, variant), re-timed the same way beside every
+    candidate, is within 5% of the fastest, and the result still matches the
+    oracle."""
+    torch, dev = torch_dev()
+    p = problem(name)
+    A = make_matrix(p)
+    rep = A.select(use_cache=False, flush_bytes=1 << 30)
+    log(f"[select cold] {name}: chose {rep['chosen']} v{rep['chosen_variant']} medians {rep['median_us']}")
+    assert rep["status"][rep["chosen"]] == 0
+    x = torch.from_numpy(x_for(p)).to(dev)
+    yref, scale = oracle.spmv_csr_ref(p.row_ptr, p.col, p.val, x_for(p))
+    assert row_scaled_err(A.spmv(x).cpu().numpy(), yref, scale) <= 1e-14
+    chosen_t, best_t, best_f = selection_retime_cold(p, A, rep)
+    log(f"[select cold] {name}: chosen {chosen_t:.2f} us, best re-timed {best_f} {best_t:.2f} us")
     assert chosen_t <= 1.05 * best_t
     A.close()
 

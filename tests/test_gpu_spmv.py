@@ -7,7 +7,7 @@ import pytest
 import inputs
 import oracle
 import paper_2209_06478_amd as dsm
-from gpu_common import FORMATS, log, make_matrix, problem, row_scaled_err, torch_dev, x_for
+from gpu_common import FORMATS, ctx, log, make_matrix, problem, row_scaled_err, torch_dev, x_for
 
 pytestmark = pytest.mark.gpu
 
@@ -32,7 +32,7 @@ def run_formats(name, formats=FORMATS, tol=1e-14):
                 out[f] = "infeasible"
                 continue
             raise
-        variants = range(8) if f == "csr" else (range(32) if f in ("dia", "hdc") else (range(16) if f in ("ell", "hyb") else [0]))
+        variants = range(8) if f == "csr" else (range(64) if f in ("dia", "hdc") else (range(16) if f in ("ell", "hyb") else [0]))
         for v in variants:
             A.variant = v
             y = A.spmv(xt)
@@ -107,7 +107,7 @@ def test_spmv_reduced_precision_values(vdt):
             log(f"[spmv-{vdt}] {name} {f}")
             # every sweep variant: the FP32/BF16 sweeps have interior paths of
             # their own (plain loads where a tile lies inside the matrix)
-            variants = range(32) if f in ("dia", "hdc") else (range(16) if f in ("ell", "hyb") else [0])
+            variants = range(64) if f in ("dia", "hdc") else (range(16) if f in ("ell", "hyb") else [0])
             for v in variants:
                 A.variant = v
                 y = A.spmv(torch.from_numpy(x).to(dev)).cpu().numpy()
@@ -176,7 +176,7 @@ def test_spmv_nonfinite_x_stays_in_its_rows(name):
             if e.status == dsm.L.E_INFEASIBLE:
                 continue
             raise
-        variants = range(8) if f == "csr" else (range(32) if f in ("dia", "hdc") else (range(16) if f in ("ell", "hyb") else [0]))
+        variants = range(8) if f == "csr" else (range(64) if f in ("dia", "hdc") else (range(16) if f in ("ell", "hyb") else [0]))
         for v in variants:
             A.variant = v
             y = A.spmv(xt).cpu().numpy()
@@ -187,3 +187,57 @@ def test_spmv_nonfinite_x_stays_in_its_rows(name):
             sel = expect_inf != 0
             assert np.array_equal(np.sign(y[sel]), expect_inf[sel]), (name, f, v)
     A.close()
+
+
+@pytest.mark.parametrize("name", ["hpcg16", "banded20k", "rect_empty"])
+def test_spmv_nontemporal_variants_bitwise(name):
+    """Bit 5 of a DIA/HDC variant changes only the cache hint of the value
+    loads: y is bitwise the same as with the variant without it."""
+    torch, dev = torch_dev()
+    p = problem(name)
+    A = make_matrix(p)
+    xt = torch.from_numpy(x_for(p)).to(dev)
+    for f in ("dia", "hdc"):
+        try:
+            A.convert(f)
+        except dsm.DsmError as e:
+            if e.status == dsm.L.E_INFEASIBLE:
+                continue
+            raise
+        for v in range(32):
+            A.variant = v
+            a = A.spmv(xt).cpu().numpy()
+            A.variant = v | 32
+            b = A.spmv(xt).cpu().numpy()
+            assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), (name, f, v)
+    A.close()
+
+
+def test_spmv_kernel_time():
+    """dsm_spmv_kernel_time computes the same y as dsm_spmv and times only
+    the kernels: positive, and at most the event pair around the call on the
+    same stream; 0 for a matrix with no rows."""
+    torch, dev = torch_dev()
+    p = problem("hpcg16")
+    A = make_matrix(p)
+    xt = torch.from_numpy(x_for(p)).to(dev)
+    for f in FORMATS:
+        A.convert(f)
+        y1 = A.spmv(xt)
+        y2 = torch.empty_like(y1)
+        ks, es = [], []
+        for _ in range(5):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            ks.append(A.kernel_time(xt, y2))
+            b.record()
+            torch.cuda.synchronize()
+            es.append(a.elapsed_time(b) * 1e3)
+        log(f"[kernel_time] {f}: kernel {np.median(ks):.2f} us, event pair {np.median(es):.2f} us")
+        assert torch.equal(y1, y2), f
+        assert all(k > 0 for k in ks) and np.median(ks) <= np.median(es), (f, ks, es)
+    A.close()
+    e = dsm.Matrix.from_csr(ctx(), 0, 5, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    assert e.kernel_time(torch.zeros(5, dtype=torch.float64, device=dev),
+                         torch.zeros(0, dtype=torch.float64, device=dev)) == 0.0
+    e.close()
