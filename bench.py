@@ -398,11 +398,13 @@ def irregular_bench(dsm, ctx, torch, dev):
     """Format selection on the irregular 1M-row matrices (Zipf row lengths,
     banded with 30% fill), FP64 and FP32 values: per-format SpMV time and
     GB/s, the chosen format and its speed-up over fixed CSR."""
+    import numpy as np
     import inputs
     out = {}
     for name, gen in (("zipf_1m", inputs.zipf), ("banded_1m", inputs.banded)):
         log(f"[bench] selection on {name}")
         p = gen()
+        bounds = gather_bounds(dsm, torch, dev, p)
         for vdt in ("f64", "f32"):
             # the cost model's pick first (no profiling runs; the model has
             # only learned from the matrices timed before this one)
@@ -428,9 +430,33 @@ def irregular_bench(dsm, ctx, torch, dev):
                                     "timed_selection_ms": round(timed_ms, 1),
                                     "model_choice": mrep["chosen"], "model_selection_ms": round(model_ms, 1),
                                     "model_choice_slowdown": round(t[mrep["chosen"]] / t[rep["chosen"]], 3)
-                                    if mrep["chosen"] in t else None}
+                                    if mrep["chosen"] in t else None,
+                                    "bounds_fp64_x": bounds}
             A.close()
     return out
+
+
+def gather_bounds(dsm, torch, dev, p, reps=20):
+    """What an SpMV of this matrix cannot beat, measured with the library's
+    probes: the x gathers alone (one FP64 gather per stored entry, at the
+    matrix's own column indices, read lane-contiguously) and a streaming
+    read of as many bytes as the CSR arrays and both vectors."""
+    import numpy as np
+    import inputs
+    col = torch.from_numpy(p.col.astype(np.int32)).to(dev)
+    x = torch.from_numpy(inputs.uniform_vector(p.ncols)).to(dev)
+    part = torch.empty(dsm.PROBE_PARTIALS, dtype=torch.float64, device=dev)
+    nbytes = p.nnz * 12 + (p.nrows + 1) * 4 + 16 * p.nrows
+    buf = torch.empty((nbytes + 15) // 16 * 2, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        dsm.gather_probe(x, col, part)
+        dsm.stream_probe("read", part, buf)
+    g = float(np.median(event_times_us(torch, lambda: dsm.gather_probe(x, col, part), reps)))
+    r = float(np.median(event_times_us(torch, lambda: dsm.stream_probe("read", part, buf), reps)))
+    del col, x, part, buf
+    return {"gather_us": round(g, 2), "gathers_per_us": round(p.nnz / g, 1),
+            "stream_read_us": round(r, 2), "stream_read_bytes": int(nbytes)}
+
 
 
 def split_bench(dsm, ctx, torch, dev, n=104):
@@ -513,6 +539,52 @@ def mg_bench(dsm, ctx, torch, dev, n=104, nlev=4):
     return out
 
 
+def spmv_leg(dsm, torch, dev, args):
+    """For kernel traces and byte counters of one kernel: `steps` SpMVs of
+    the chosen matrix in --format / --variant (CSR and variant 0 by
+    default), back to back after `warmup`, then the gather and streaming
+    probes of the same matrix and, with --copy-mb, the calibration copy."""
+    import numpy as np
+    import inputs
+    gen = {"hpcg": lambda: inputs.hpcg27(args.n), "aniso7": lambda: inputs.aniso7(args.n), "zipf": inputs.zipf,
+           "banded": inputs.banded}[args.matrix]
+    log(f"[bench] generating {args.matrix}")
+    p = gen()
+    ctx = dsm.Context(0)
+    A = dsm.Matrix.from_csr(ctx, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
+    A.convert(args.format or "csr", value_dtype=args.value_dtype)
+    A.variant = args.variant or 0
+    vt = torch.float64 if args.vec_dtype == "f64" else torch.float32
+    x = torch.from_numpy(inputs.uniform_vector(p.ncols)).to(dev).to(vt)
+    y = torch.empty(p.nrows, dtype=vt, device=dev)
+    for _ in range(args.warmup):
+        A.spmv(x, out=y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        A.spmv(x, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    avg = e0.elapsed_time(e1) * 1e3 / args.steps
+    info = A.info()
+    v = {"f64": 8, "f32": 4, "bf16": 2}[args.value_dtype]
+    nb = alg_bytes(info, p.nrows, p.nnz, v=v, X=8 if args.vec_dtype == "f64" else 4)
+    out = {"matrix": p.name, "nrows": p.nrows, "nnz": p.nnz, "format": info["format_name"], "variant": A.variant,
+           "value_dtype": args.value_dtype, "vec_dtype": args.vec_dtype, "steps": args.steps, "avg_us": round(avg, 3),
+           "algorithmic_bytes": int(nb), **spmv_rates(nb, p.nnz, avg),
+           "bounds_fp64_x": gather_bounds(dsm, torch, dev, p)}
+    A.close()
+    if args.copy_mb > 0:
+        nel = args.copy_mb * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        out["copy_avg_us"] = round(float(np.mean(event_times_us(torch, lambda: dst.copy_(src), 5))), 3)
+        out["copy_mb"] = args.copy_mb
+        del src, dst
+    ctx.close()
+    return out
+
+
 def spmv_rates(nbytes, nnz, us):
     return {"gbps": round(nbytes / (us * 1e-6) / 1e9, 1), "gflops": round(2 * nnz / (us * 1e-6) / 1e9, 1)}
 
@@ -575,11 +647,16 @@ def main():
     ap.add_argument("--cold-only", action="store_true",
                     help="after the set-up, run only the cold-cache launches (for kernel traces of them)")
     ap.add_argument("--leg", default=None,
-                    choices=["cg", "pcg_mg", "ir_cg", "split", "irregular", "serving", "small"],
+                    choices=["cg", "pcg_mg", "ir_cg", "split", "irregular", "serving", "small", "spmv"],
                     help="run only this leg (after the matrix set-up) and print its JSON; for profiling")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, run a device copy of this many MiB `steps` times "
                          "(calibration kernel of known size for the HBM byte counters)")
+    ap.add_argument("--matrix", default="hpcg", choices=["hpcg", "aniso7", "zipf", "banded"],
+                    help="with --leg spmv: HPCG n^3, ANISO7 n^3, the 1M-row Zipf matrix or the 1M-row banded matrix")
+    ap.add_argument("--value-dtype", default="f64", choices=["f64", "f32", "bf16"],
+                    help="with --leg spmv: stored value type")
+    ap.add_argument("--vec-dtype", default="f64", choices=["f64", "f32"], help="with --leg spmv: x and y type")
     ap.add_argument("--cpu-leg", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -603,6 +680,9 @@ def main():
     import paper_2209_06478_amd as dsm
 
     dev = torch.device("cuda:0")
+    if args.leg == "spmv":
+        print(json.dumps({"leg": "spmv", "result": spmv_leg(dsm, torch, dev, args)}), flush=True)
+        return
     log(f"[bench] generating hpcg27_{args.n}")
     p = inputs.hpcg27(args.n)
     ctx = dsm.Context(0)

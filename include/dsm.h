@@ -246,9 +246,10 @@ dsm_status dsm_spmv_noalloc(dsm_matrix m, const void *x, void *y, dsm_dtype vec_
  * block (Section V-A, Fig. 2; Section V-E) - add into one y. */
 dsm_status dsm_spmv_accumulate(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, void *stream);
 
-/* Kernel variant used for SpMV.  CSR (0..7): 0 = adaptive row blocks in
+/* Kernel variant used for SpMV.  CSR (0..15): 0 = adaptive row blocks in
  * XCD-aware order, 1..6 = vector kernel with 2^v lanes per row, 7 = adaptive
- * row blocks in launch order.  DIA, ELL and the DIA/ELL parts of HDC/HYB
+ * row blocks in launch order; bit 3 (8..15) loads the column indices and
+ * values with a nontemporal hint (identical results).  DIA, ELL and the DIA/ELL parts of HDC/HYB
  * (0..15): bit 0 = launch order instead of XCD-aware order, bits 1-2 =
  * log2 of the row groups per thread (1, 2, 4, 4), bit 3 = groups of two
  * adjacent rows fetched with double-width loads.  DIA and HDC also take

@@ -107,11 +107,18 @@ def hpcg27(n):
 
 def hpcg27_levels(n, nlev=4):
     """HPCG's multigrid hierarchy: the 27-point problem on n^3, (n/2)^3, ...
-    (n divisible by 2^(nlev-1)).  Per level: the Problem, the 8-colour
-    parity colouring colour = (ix & 1) + 2 (iy & 1) + 4 (iz & 1) (rows of
-    one colour share no stencil entry), and, for every level but the
-    coarsest, f2c: the fine row under each row of the next level (coarse
-    point (ix, iy, iz) sits on fine point (2 ix, 2 iy, 2 iz))."""
+    (n divisible by 2^(nlev-1)).  Per level: the Problem, an 8-colour
+    parity colouring (rows of one colour share no stencil entry), and, for
+    every level but the coarsest, f2c: the fine row under each row of the
+    next level (coarse point (ix, iy, iz) sits on fine point (2 ix, 2 iy,
+    2 iz)).
+
+    colour = 7 - ((ix & 1) + 2 (iy & 1) + 4 (iz & 1)): the all-even points,
+    where the residual is injected, form colour 7, the colour a forward
+    sweep visits last and a backward sweep first.  Had they been the colour
+    the pre-smoothing sweep updates last, each of them would be solved
+    exactly against neighbours that no longer change, the injected residual
+    would be rounding noise and the coarse levels would add nothing."""
     if n % (1 << (nlev - 1)):
         raise ValueError(f"n={n} is not divisible by 2^{nlev - 1}")
     levels = []
@@ -119,7 +126,7 @@ def hpcg27_levels(n, nlev=4):
         m = n >> l
         idx = np.arange(m ** 3, dtype=np.int64)
         ix, iy, iz = idx % m, (idx // m) % m, idx // (m * m)
-        colour = ((ix & 1) + 2 * (iy & 1) + 4 * (iz & 1)).astype(np.int32)
+        colour = (7 - ((ix & 1) + 2 * (iy & 1) + 4 * (iz & 1))).astype(np.int32)
         lv = {"problem": hpcg27(m), "colour": colour}
         if l < nlev - 1:
             c = m // 2

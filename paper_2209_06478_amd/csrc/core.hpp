@@ -193,7 +193,8 @@ size_t spmv_scratch_bytes(const dsm_matrix_s *m, const Payload &P, int vec_dtype
 double spmv_bytes(const dsm_matrix_s *m, const Payload &P, int vec_dtype);
 // Number of CSR kernel variants (index 0 = adaptive) and of DIA/ELL sweep
 // variants (tile order x row groups per thread x paired rows).
-constexpr int CSR_VARIANTS = 8;
+constexpr int CSR_VARIANTS = 16;
+constexpr int CSR_VARIANT_NT = 8;
 constexpr int SWEEP_VARIANT_COUNT = 16;
 // DIA/HDC also take bit 4 (x staged in LDS per diagonal cluster) and bit 5
 // (value loads marked nontemporal).

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "cg_common.hpp"
@@ -48,7 +49,13 @@ struct dsm_mg_s {
         int32_t *rows = nullptr;        // rows grouped by colour, ascending inside a colour
         double *diag = nullptr;
         int32_t *f2c = nullptr;         // next level's rows -> rows of this level
-        double *dperm = nullptr;        // DIA: diagonals in colour order (same pitch)
+        int64_t f2c_t0 = -1;            // >= 0: f2c lists rows[f2c_t0 ...] (one colour, in order)
+        double *dperm = nullptr;        // DIA: diagonals in colour order (same pitch), the main diagonal last
+        int32_t *offnd = nullptr;       // DIA: offsets of the other diagonals, ascending
+        int kd = -1;                    // DIA: index of offset 0 among the ascending offsets
+        double *rec = nullptr;          // DIA levels swept in LDS: one record of lds_rw doubles per slot
+        int lds_nd = 0;                 // > 0: the level takes the LDS sweep with this many diagonals
+        int64_t guard = 0;              // largest |offset| (zero guard band around x in LDS)
         int64_t *cstart_d = nullptr;    // cstart on the device (one-workgroup sweep)
         double *r = nullptr, *x = nullptr;
         dsm::Workspace spws;
@@ -123,15 +130,19 @@ __global__ void __launch_bounds__(MB) k_symgs_csr(i64 cnt, const i32 *__restrict
     if (g < cnt && lane == 0 && !halt) x[i] = (r[i] - s) / diag[i];
 }
 
-// DIA levels keep a colour-ordered copy of the diagonals: slot t of
-// diagonal k holds A(rows[t], rows[t] + off_k), so a colour's rows are a
-// contiguous, coalesced range of every diagonal (in the natural layout they
-// would be every other slot, wasting half of each line fetched).
+// DIA levels keep a colour-ordered copy of the diagonals: slot t of copy
+// k holds A(rows[t], rows[t] + offnd_k) for the off-diagonals in ascending
+// offset order, and the last copy holds the main diagonal A(rows[t],
+// rows[t]).  A colour's rows are then a contiguous, coalesced range of
+// every copy (in the natural layout they would be every other slot,
+// wasting half of each line fetched), and the divisor is read with them
+// instead of gathered at row rows[t].  nod = ndiag - 1 off-diagonals.
+__device__ __forceinline__ i64 slot_of(i64 k, i64 kd, i64 ndiag) { return k < kd ? k : (k == kd ? ndiag - 1 : k - 1); }
+
 template <int R>
-__global__ void __launch_bounds__(MB) k_symgs_dia(i64 t0, i64 cnt, const i32 *__restrict__ rows, i64 n, i64 ndiag,
-                                                  const i32 *__restrict__ offs, const double *__restrict__ dperm,
-                                                  i64 pitch, const double *__restrict__ diag,
-                                                  const double *__restrict__ r, double *__restrict__ x,
+__global__ void __launch_bounds__(MB) k_symgs_dia(i64 t0, i64 cnt, const i32 *__restrict__ rows, i64 n, i64 nod,
+                                                  const i32 *__restrict__ offnd, const double *__restrict__ dperm,
+                                                  i64 pitch, const double *__restrict__ r, double *__restrict__ x,
                                                   const int *stop) {
     const bool halt = stopped(stop);
     // R rows per thread, each with its own sum, and the diagonal loop
@@ -150,14 +161,17 @@ __global__ void __launch_bounds__(MB) k_symgs_dia(i64 t0, i64 cnt, const i32 *__
         i[q] = g < cnt ? rows[t0 + g] : -1;
         s[q] = 0;
     }
-#pragma unroll 27
-    for (i64 k = 0; k < ndiag; k++) {
-        const i64 off = offs[k];
+    double d[R];
+#pragma unroll
+    for (int q = 0; q < R; q++) d[q] = dperm[nod * pitch + t0 + gq[q]];
+#pragma unroll 26
+    for (i64 k = 0; k < nod; k++) {
+        const i64 off = offnd[k];
         const double *dk = dperm + k * pitch + t0;
 #pragma unroll
         for (int q = 0; q < R; q++) {
             const i64 j = i[q] + off;
-            const bool ok = off != 0 && i[q] >= 0 && j >= 0 && j < n;
+            const bool ok = i[q] >= 0 && j >= 0 && j < n;
             const double v = dk[gq[q]];
             const double xv = x[ok ? j : 0];
             s[q] += ok ? v * xv : 0.0;
@@ -165,16 +179,80 @@ __global__ void __launch_bounds__(MB) k_symgs_dia(i64 t0, i64 cnt, const i32 *__
     }
 #pragma unroll
     for (int q = 0; q < R; q++)
-        if (i[q] >= 0 && !halt) x[i[q]] = (r[i[q]] - s[q]) / diag[i[q]];
+        if (i[q] >= 0 && !halt) x[i[q]] = (r[i[q]] - s[q]) / d[q];
 }
 
-__global__ void k_dia_colour_order(i64 n, i64 ndiag, const double *__restrict__ dval, i64 pitch,
+// The per-colour sweep for levels of ND diagonals (7 or 27): the ND values
+// of the thread's slot (off-diagonals, then the main diagonal) are loaded
+// first, since they do not depend on the row index; then the row index,
+// then every x gather and r.  The loads go into arrays in separate loops so
+// that all of them are in flight together (the runtime-length loop above
+// lets the compiler interleave loads and products, which reuses registers
+// and keeps only a few loads in flight).
+template <int ND, bool XCD, bool NT>
+__global__ void __launch_bounds__(MB) k_symgs_dia_nd(i64 t0, i64 cnt, const i32 *__restrict__ rows, i64 n,
+                                                     const i32 *__restrict__ offnd, const double *__restrict__ dperm,
+                                                     i64 pitch, const double *__restrict__ r, double *__restrict__ x,
+                                                     const int *stop) {
+#pragma clang fp contract(off)
+    const bool halt = stopped(stop);
+    const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const i64 g = (i64)b * MB + threadIdx.x;
+    if (g >= cnt) return;
+    const i64 t = t0 + g;
+    double v[ND];
+    const double *p = dperm + t;
+#pragma unroll
+    for (int k = 0; k < ND; k++) {
+        v[k] = ld_stream<double, NT>(p);
+        p += pitch;
+    }
+    const i64 i = rows[t];
+    double xv[ND - 1];
+#pragma unroll
+    for (int k = 0; k < ND - 1; k++) {
+        const i64 j = i + offnd[k];
+        xv[k] = x[(j >= 0 && j < n) ? j : 0];
+    }
+    const double ri = r[i];
+    double s = 0;
+#pragma unroll
+    for (int k = 0; k < ND - 1; k++) {
+        const i64 j = i + offnd[k];
+        s = s + ((j >= 0 && j < n) ? v[k] * xv[k] : 0.0);
+    }
+    if (!halt) x[i] = (ri - s) / v[ND - 1];
+}
+
+__global__ void k_dia_colour_order(i64 n, i64 ndiag, i64 kd, const double *__restrict__ dval, i64 pitch,
                                    const i32 *__restrict__ rows, double *__restrict__ dperm) {
     const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const i64 i = rows[t];
-    for (i64 k = 0; k < ndiag; k++) dperm[k * pitch + t] = dval[k * pitch + i];
+    for (i64 k = 0; k < ndiag; k++) dperm[slot_of(k, kd, ndiag) * pitch + t] = dval[k * pitch + i];
 }
+
+// Records of the LDS sweep: slot t holds the ND values of row rows[t] in the
+// colour-ordered copy's order (off-diagonals ascending, then the main
+// diagonal) followed by the row index itself, so one contiguous record load
+// gives a thread everything about its row but x and r.
+template <int ND>
+__global__ void k_lds_records(i64 n, i64 kd, const double *__restrict__ dval, i64 pitch, const i32 *__restrict__ rows,
+                              double *__restrict__ rec) {
+    constexpr int RW = ND + 1;
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const i64 i = rows[t];
+    for (i64 k = 0; k < ND; k++) rec[t * RW + slot_of(k, kd, ND)] = dval[k * pitch + i];
+    rec[t * RW + ND] = __builtin_bit_cast(double, i);
+}
+
+// DSM_MG_LDS=0 turns the LDS sweep off (small levels then take the
+// one-workgroup sweep through the L2), DSM_MG_ND=0 the fixed-length colour
+// sweeps (the runtime-length sweep then runs), to time one against the other.
+static bool lds_sweep_on();
+static bool nd_sweep_on();
+static int mg_variant();
 
 // Small levels: the whole sweep (every colour, forward then backward) in
 // one workgroup, colours separated by barriers, instead of one launch per
@@ -185,10 +263,9 @@ constexpr i64 BLOCK_LEVEL_ROWS = 8192;    // levels up to this size use it
 __device__ __forceinline__ int sweep_colour(int step, int nc) { return step < nc ? step : 2 * nc - 2 - step; }
 
 __global__ void __launch_bounds__(SBT) k_symgs_dia_block(int nc, const i64 *__restrict__ cstart,
-                                                         const i32 *__restrict__ rows, i64 n, i64 ndiag,
-                                                         const i32 *__restrict__ offs,
+                                                         const i32 *__restrict__ rows, i64 n, i64 nod,
+                                                         const i32 *__restrict__ offnd,
                                                          const double *__restrict__ dperm, i64 pitch,
-                                                         const double *__restrict__ diag,
                                                          const double *__restrict__ r, double *x, const int *stop,
                                                          int from_zero) {
     if (stopped(stop)) return;
@@ -203,18 +280,84 @@ __global__ void __launch_bounds__(SBT) k_symgs_dia_block(int nc, const i64 *__re
             const i64 i = rows[t];
             double s = 0;
 #pragma unroll 9
-            for (i64 k = 0; k < ndiag; k++) {
-                const i64 off = offs[k];
-                const i64 j = i + off;
-                const bool ok = off != 0 && j >= 0 && j < n;
+            for (i64 k = 0; k < nod; k++) {
+                const i64 j = i + offnd[k];
+                const bool ok = j >= 0 && j < n;
                 const double v = dperm[k * pitch + t];
                 const double xv = x[ok ? j : 0];
                 s += ok ? v * xv : 0.0;
             }
-            x[i] = (r[i] - s) / diag[i];
+            x[i] = (r[i] - s) / dperm[nod * pitch + t];
         }
         __syncthreads();  // the next colour reads this colour's updates
     }
+}
+
+// Small DIA levels whose colours have at most LT rows: the whole sweep in
+// one workgroup of LT threads with the level's x and r held in LDS (x with
+// a zero guard band of the largest |offset| on each side, so a neighbour
+// outside the matrix reads +0 and needs no test).  Each step updates one
+// colour, a thread owning at most one of its rows: it loads the row's
+// record (values and row index; fourteen 16-byte loads in flight at once),
+// reads x and r in LDS and writes its x there.  Per step the critical path
+// is one record load, the LDS reads and a barrier that orders LDS only,
+// instead of the row index, then gathers of x and r from the L2, then a
+// store of x to it.  The sums are the same products in the same order as
+// the other sweeps (no fused multiply-add).
+constexpr int LT = 512;
+constexpr i64 LDS_WORDS = 20000;  // 160,000 bytes: x with its guard bands, then r
+
+template <int ND>
+__device__ __forceinline__ void load_record(const double *__restrict__ rec, i64 t, double (&v)[ND + 1]) {
+    constexpr int RW = ND + 1;
+    static_assert(RW % 2 == 0, "records are whole 16-byte words");
+    const double2 *p = (const double2 *)(rec + t * RW);
+#pragma unroll
+    for (int k = 0; k < RW / 2; k++) {
+        const double2 w = p[k];
+        v[2 * k] = w.x;
+        v[2 * k + 1] = w.y;
+    }
+}
+
+template <int ND>
+__global__ void __launch_bounds__(LT) k_symgs_dia_lds(int nc, const i64 *__restrict__ cstart, i64 n, i64 G,
+                                                      const i32 *__restrict__ offnd, const double *__restrict__ rec,
+                                                      const double *__restrict__ r, double *x, const int *stop,
+                                                      int from_zero) {
+#pragma clang fp contract(off)
+    __shared__ double sm[LDS_WORDS];
+    double *xs = sm + G;           // x[j] at xs[j], j in [-G, n + G)
+    double *rs = sm + n + 2 * G;   // r[i] at rs[i]
+    if (stopped(stop)) return;
+    for (i64 k = threadIdx.x; k < n + 2 * G; k += LT) {
+        const i64 j = k - G;
+        sm[k] = (from_zero || j < 0 || j >= n) ? 0.0 : x[j];
+    }
+    for (i64 k = threadIdx.x; k < n; k += LT) rs[k] = r[k];
+    i32 o[ND - 1];
+#pragma unroll
+    for (int k = 0; k < ND - 1; k++) o[k] = offnd[k];
+    __syncthreads();
+    for (int step = 0; step < 2 * nc - 1; step++) {
+        const int c = sweep_colour(step, nc);
+        const i64 t = cstart[c] + threadIdx.x;
+        if (t < cstart[c + 1]) {
+            double v[ND + 1];
+            load_record<ND>(rec, t, v);
+            const i64 i = __builtin_bit_cast(i64, v[ND]);
+            double s = 0;
+#pragma unroll
+            for (int k = 0; k < ND - 1; k++) s = s + v[k] * xs[i + o[k]];
+            xs[i] = (rs[i] - s) / v[ND - 1];
+        }
+        // orders the LDS updates only (no global store is read in the sweep)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    }
+    __syncthreads();
+    for (i64 i = threadIdx.x; i < n; i += LT) x[i] = xs[i];
 }
 
 template <int W>
@@ -263,13 +406,13 @@ __global__ void __launch_bounds__(SBT) k_symgs_csr_block(int nc, const i64 *__re
 // other row starts at 0.  Replaces the zeroing launch and the first colour
 // launch.  t walks the colour-ordered rows, colour 0 being [0, n0).
 __global__ void k_symgs_first_from_zero(i64 n, i64 n0, const i32 *__restrict__ rows,
-                                        const double *__restrict__ diag, const double *__restrict__ r,
-                                        double *__restrict__ x, const int *stop) {
+                                        const double *__restrict__ diag, int by_slot,
+                                        const double *__restrict__ r, double *__restrict__ x, const int *stop) {
     const bool halt = stopped(stop);
     const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const i64 i = rows[t];
-    const double v = t < n0 ? (r[i] - 0.0) / diag[i] : 0.0;
+    const double v = t < n0 ? (r[i] - 0.0) / diag[by_slot ? t : i] : 0.0;
     if (!halt) x[i] = v;
 }
 
@@ -298,6 +441,33 @@ __global__ void __launch_bounds__(MB) k_restrict_dia(i64 nc, const i32 *__restri
         const i64 j = i + offs[k];
         const bool ok = j >= 0 && j < n;
         const double v = dval[k * pitch + i];
+        const double xv = x[ok ? j : 0];
+        s += ok ? v * xv : 0.0;
+    }
+    if (!halt) rc[c] = r[i] - s;
+}
+
+// The same residual when the coarse points are exactly one colour of the
+// level, listed in the colour's row order: coarse row c sits on slot
+// t0 + c of the colour-ordered diagonals, so the values come from one
+// contiguous range of each diagonal instead of every other row of every
+// other grid line.  Same products in the same order as k_restrict_dia.
+__global__ void __launch_bounds__(MB) k_restrict_dia_perm(i64 nc, i64 t0, const i32 *__restrict__ f2c, i64 n,
+                                                          i64 ndiag, i64 kd, const i32 *__restrict__ offs,
+                                                          const double *__restrict__ dperm, i64 pitch,
+                                                          const double *__restrict__ x, const double *__restrict__ r,
+                                                          double *__restrict__ rc, const int *stop) {
+    const bool halt = stopped(stop);
+    const i64 c = (i64)blockIdx.x * MB + threadIdx.x;
+    if (c >= nc) return;
+    const i64 i = f2c[c];
+    const double *dp = dperm + t0 + c;
+    double s = 0;
+#pragma unroll 27
+    for (i64 k = 0; k < ndiag; k++) {
+        const i64 j = i + offs[k];
+        const bool ok = j >= 0 && j < n;
+        const double v = dp[slot_of(k, kd, ndiag) * pitch];
         const double xv = x[ok ? j : 0];
         s += ok ? v * xv : 0.0;
     }
@@ -516,13 +686,23 @@ static void symgs(dsm_mg_s *mg, int l, const double *r, double *x, hipStream_t s
     const Payload &P = lv.A->P;
     const int nc = (int)lv.cstart.size() - 1;
     if (nc == 0) return;
+    if (lv.lds_nd > 0 && lds_sweep_on()) {
+        if (lv.lds_nd == 27)
+            hipLaunchKernelGGL(k_symgs_dia_lds<27>, dim3(1), dim3(LT), 0, s, nc, lv.cstart_d, lv.n, lv.guard,
+                               lv.offnd, lv.rec, r, x, stop, (int)from_zero);
+        else
+            hipLaunchKernelGGL(k_symgs_dia_lds<7>, dim3(1), dim3(LT), 0, s, nc, lv.cstart_d, lv.n, lv.guard,
+                               lv.offnd, lv.rec, r, x, stop, (int)from_zero);
+        DSM_HIP(hipGetLastError());
+        return;
+    }
     if (lv.n <= BLOCK_LEVEL_ROWS) {
         if (lv.fmt == DSM_CSR)
             hipLaunchKernelGGL(k_symgs_csr_block<GSW>, dim3(1), dim3(SBT), 0, s, nc, lv.cstart_d, lv.rows, P.rp,
                                P.col, (const double *)P.val, lv.diag, r, x, stop, lv.n, (int)from_zero);
         else
-            hipLaunchKernelGGL(k_symgs_dia_block, dim3(1), dim3(SBT), 0, s, nc, lv.cstart_d, lv.rows, lv.n, P.ndiag,
-                               P.offs, lv.dperm, P.pitch, lv.diag, r, x, stop, (int)from_zero);
+            hipLaunchKernelGGL(k_symgs_dia_block, dim3(1), dim3(SBT), 0, s, nc, lv.cstart_d, lv.rows, lv.n,
+                               P.ndiag - 1, lv.offnd, lv.dperm, P.pitch, r, x, stop, (int)from_zero);
         DSM_HIP(hipGetLastError());
         return;
     }
@@ -532,19 +712,61 @@ static void symgs(dsm_mg_s *mg, int l, const double *r, double *x, hipStream_t s
         if (lv.fmt == DSM_CSR)
             hipLaunchKernelGGL(k_symgs_csr<GSW>, dim3(grid_for(cnt * GSW, MB)), dim3(MB), 0, s, cnt, lv.rows + c0,
                                P.rp, P.col, (const double *)P.val, lv.diag, r, x, stop);
+        else if ((P.ndiag == 27 || P.ndiag == 7) && nd_sweep_on()) {
+            const dim3 g(grid_for(cnt, MB)), bl(MB);
+            const int mv = mg_variant();
+#define ND_LAUNCH(ND)                                                                                           \
+    switch (mv) {                                                                                               \
+    case 1: hipLaunchKernelGGL((k_symgs_dia_nd<ND, true, false>), g, bl, 0, s, c0, cnt, lv.rows, lv.n, lv.offnd, \
+                               lv.dperm, P.pitch, r, x, stop); break;                                           \
+    case 2: hipLaunchKernelGGL((k_symgs_dia_nd<ND, false, true>), g, bl, 0, s, c0, cnt, lv.rows, lv.n, lv.offnd, \
+                               lv.dperm, P.pitch, r, x, stop); break;                                           \
+    case 3: hipLaunchKernelGGL((k_symgs_dia_nd<ND, true, true>), g, bl, 0, s, c0, cnt, lv.rows, lv.n, lv.offnd,  \
+                               lv.dperm, P.pitch, r, x, stop); break;                                           \
+    default: hipLaunchKernelGGL((k_symgs_dia_nd<ND, false, false>), g, bl, 0, s, c0, cnt, lv.rows, lv.n,       \
+                                lv.offnd, lv.dperm, P.pitch, r, x, stop); break;                                \
+    }
+            if (P.ndiag == 27) { ND_LAUNCH(27) } else { ND_LAUNCH(7) }
+#undef ND_LAUNCH
+        }
         else
             hipLaunchKernelGGL(k_symgs_dia<GSR>, dim3(grid_for(cnt, MB * GSR)), dim3(MB), 0, s, c0, cnt, lv.rows,
-                               lv.n, P.ndiag, P.offs, lv.dperm, P.pitch, lv.diag, r, x, stop);
+                               lv.n, P.ndiag - 1, lv.offnd, lv.dperm, P.pitch, r, x, stop);
     };
     int c_first = 0;
     if (from_zero) {
+        const bool dia = lv.fmt == DSM_DIA;
         hipLaunchKernelGGL(k_symgs_first_from_zero, dim3(grid_for(lv.n, MB)), dim3(MB), 0, s, lv.n, lv.cstart[1],
-                           lv.rows, lv.diag, r, x, stop);
+                           lv.rows, dia ? lv.dperm + (P.ndiag - 1) * P.pitch : lv.diag, (int)dia, r, x, stop);
         c_first = 1;
     }
     for (int c = c_first; c < nc; c++) colour(c);
     for (int c = nc - 2; c >= 0; c--) colour(c);
     DSM_HIP(hipGetLastError());
+}
+
+static int mg_variant() {
+    static const int v = [] {
+        const char *e = getenv("DSM_MG_VARIANT");
+        return e ? atoi(e) & 3 : 0;
+    }();
+    return v;
+}
+
+static bool nd_sweep_on() {
+    static const bool v = [] {
+        const char *e = getenv("DSM_MG_ND");
+        return !(e && e[0] == '0');
+    }();
+    return v;
+}
+
+static bool lds_sweep_on() {
+    static const bool v = [] {
+        const char *e = getenv("DSM_MG_LDS");
+        return !(e && e[0] == '0');
+    }();
+    return v;
 }
 
 // x = M r on level l (x is overwritten; one V-cycle from zero)
@@ -555,7 +777,10 @@ static void vcycle(dsm_mg_s *mg, int l, const double *r, double *x, hipStream_t 
     if (l + 1 == (int)mg->L.size()) return;
     auto &cv = mg->L[l + 1];
     const Payload &P = lv.A->P;
-    if (lv.fmt == DSM_DIA)
+    if (lv.fmt == DSM_DIA && lv.f2c_t0 >= 0)
+        hipLaunchKernelGGL(k_restrict_dia_perm, dim3(grid_for(cv.n, MB)), dim3(MB), 0, s, cv.n, lv.f2c_t0, lv.f2c,
+                           lv.n, P.ndiag, (i64)lv.kd, P.offs, lv.dperm, P.pitch, x, r, cv.r, stop);
+    else if (lv.fmt == DSM_DIA)
         hipLaunchKernelGGL(k_restrict_dia, dim3(grid_for(cv.n, MB)), dim3(MB), 0, s, cv.n, lv.f2c, lv.n, P.ndiag,
                            P.offs, (const double *)P.dval, P.pitch, x, r, cv.r, stop);
     else
@@ -635,10 +860,41 @@ static void build_level(dsm_mg_s *mg, int l, dsm_matrix A, const int32_t *colour
     cleanup();
     if (lv.fmt == DSM_DIA && n > 0) {
         const Payload &P = A->P;
+        // the main diagonal's position among the ascending offsets (every
+        // row has a nonzero diagonal, checked above, so offset 0 is stored)
+        std::vector<int32_t> offs((size_t)P.ndiag);
+        DSM_HIP(hipMemcpyAsync(offs.data(), P.offs, sizeof(int32_t) * offs.size(), hipMemcpyDeviceToHost, s));
+        DSM_HIP(hipStreamSynchronize(s));
+        std::vector<int32_t> offnd;
+        for (i64 k = 0; k < P.ndiag; k++) {
+            if (offs[k] == 0) lv.kd = (int)k;
+            else offnd.push_back(offs[k]);
+            lv.guard = std::max<int64_t>(lv.guard, std::abs((int64_t)offs[k]));
+        }
+        DSM_CHECK(lv.kd >= 0, DSM_E_INVALID, "level " + std::to_string(l) + " stores no main diagonal");
+        lv.offnd = (int32_t *)mg->alloc(sizeof(int32_t) * std::max<size_t>(offnd.size(), 1));
+        if (!offnd.empty())
+            DSM_HIP(hipMemcpyAsync(lv.offnd, offnd.data(), sizeof(int32_t) * offnd.size(), hipMemcpyHostToDevice, s));
         lv.dperm = (double *)mg->alloc(sizeof(double) * (size_t)std::max<i64>(P.ndiag * P.pitch, 1));
-        hipLaunchKernelGGL(k_dia_colour_order, dim3(grid_for(n, MB)), dim3(MB), 0, s, n, P.ndiag,
+        hipLaunchKernelGGL(k_dia_colour_order, dim3(grid_for(n, MB)), dim3(MB), 0, s, n, P.ndiag, (i64)lv.kd,
                            (const double *)P.dval, P.pitch, lv.rows, lv.dperm);
         DSM_HIP(hipGetLastError());
+        // the LDS sweep: a 7- or 27-diagonal level whose colours have at
+        // most LT rows and whose x (with guard bands) and r fit the LDS
+        i64 maxc = 0;
+        for (size_t c = 0; c + 1 < lv.cstart.size(); c++) maxc = std::max<i64>(maxc, lv.cstart[c + 1] - lv.cstart[c]);
+        if ((P.ndiag == 27 || P.ndiag == 7) && maxc <= LT && 2 * n + 2 * lv.guard <= LDS_WORDS) {
+            lv.lds_nd = (int)P.ndiag;
+            const int rw = lv.lds_nd + 1;
+            lv.rec = (double *)mg->alloc(sizeof(double) * (size_t)(n * rw));
+            if (lv.lds_nd == 27)
+                hipLaunchKernelGGL(k_lds_records<27>, dim3(grid_for(n, MB)), dim3(MB), 0, s, n, (i64)lv.kd,
+                                   (const double *)P.dval, P.pitch, lv.rows, lv.rec);
+            else
+                hipLaunchKernelGGL(k_lds_records<7>, dim3(grid_for(n, MB)), dim3(MB), 0, s, n, (i64)lv.kd,
+                                   (const double *)P.dval, P.pitch, lv.rows, lv.rec);
+            DSM_HIP(hipGetLastError());
+        }
         DSM_HIP(hipStreamSynchronize(s));
     }
     if (l > 0) {
@@ -653,6 +909,14 @@ static void build_level(dsm_mg_s *mg, int l, dsm_matrix A, const int32_t *colour
             DSM_CHECK(f >= 0 && f < n && !seen[f], DSM_E_INVALID,
                       "f2c of level " + std::to_string(l) + " must map coarse rows to distinct rows of the level");
             seen[f] = 1;
+        }
+        // the coarse points are one whole colour, in that colour's row order
+        for (size_t c = 0; c + 1 < lv.cstart.size(); c++) {
+            const i64 t0 = lv.cstart[c];
+            if (lv.cstart[c + 1] - t0 != n_next || n_next == 0) continue;
+            bool same = true;
+            for (i64 k = 0; k < n_next && same; k++) same = rows[t0 + k] == f2c_h[k];
+            if (same) lv.f2c_t0 = t0;
         }
         lv.f2c = (int32_t *)mg->alloc(sizeof(int32_t) * (size_t)std::max<i64>(n_next, 1));
         if (n_next > 0)

@@ -394,7 +394,7 @@ void select_format(dsm_matrix m, uint32_t mask, const dsm_select_opts &o, dsm_se
             if (o.target == 1) {
                 variants = f == DSM_CSR ? std::vector<int>{1, 2, 4, 8, 16, 32} : std::vector<int>{1};
             } else if (o.tune_variant) {
-                if (f == DSM_CSR) variants = {0, 7, 2, 3, 4, 5, 6};
+                if (f == DSM_CSR) variants = {0, 7, 8, 15, 2, 3, 4, 5, 6};
                 else if (f == DSM_DIA || f == DSM_HDC)
                     variants = {0, 1, 2, 4, 8, 10, 12, 16, 18, 20, 19, 21, 32, 40, 48, 56, 50, 58};
                 else if (f == DSM_ELL || f == DSM_HYB) variants = {0, 1, 2, 4, 8, 10, 12};

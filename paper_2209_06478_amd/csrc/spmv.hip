@@ -105,7 +105,7 @@ __device__ __forceinline__ void store_y(X *y, i64 i, X v, bool acc) {
 }
 
 // ---------------------------------------------------------------- CSR
-template <class V, class X, bool ACC, bool XCD>
+template <class V, class X, bool ACC, bool XCD, bool NT = false>
 __global__ void __launch_bounds__(SB) k_csr_adaptive(const i32 *__restrict__ blocks, const i32 *__restrict__ rp,
                                                      const i32 *__restrict__ col, const V *__restrict__ val,
                                                      const X *__restrict__ x, X *__restrict__ y,
@@ -132,8 +132,8 @@ __global__ void __launch_bounds__(SB) k_csr_adaptive(const i32 *__restrict__ blo
 #pragma unroll
             for (int u = 0; u < CU; u++) {
                 const i64 e = base + (i64)u * SB;
-                c[u] = *(e < e1 ? col + e : sentinel_ptr<i32>());
-                v[u] = *(e < e1 ? val + e : zero_ptr<V>());
+                c[u] = load_val<NT>(e < e1 ? col + e : sentinel_ptr<i32>());
+                v[u] = load_val<NT>(e < e1 ? val + e : zero_ptr<V>());
             }
 #pragma unroll
             for (int u = 0; u < CU; u++) xv[u] = *(c[u] >= 0 ? x + c[u] : zero_ptr<X>());
@@ -157,8 +157,8 @@ __global__ void __launch_bounds__(SB) k_csr_adaptive(const i32 *__restrict__ blo
         for (int u = 0; u < PU; u++) {
             const int k = tid + u * SB;
             if (k < ne) {
-                c[u] = col[e0 + k];
-                v[u] = val[e0 + k];
+                c[u] = load_val<NT>(col + e0 + k);
+                v[u] = load_val<NT>(val + e0 + k);
             }
         }
 #pragma unroll
@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(SB) k_csr_adaptive(const i32 *__restrict__ blo
     if (rl < nr && lane == 0) store_y(y, r0 + rl, s, ACC);
 }
 
-template <class V, class X, int W, bool ACC>
+template <class V, class X, int W, bool ACC, bool NT = false>
 __global__ void __launch_bounds__(SB) k_csr_vector(i64 nrows, const i32 *__restrict__ rp, const i32 *__restrict__ col,
                                                    const V *__restrict__ val, const X *__restrict__ x,
                                                    X *__restrict__ y, const int *__restrict__ stop) {
@@ -202,8 +202,8 @@ __global__ void __launch_bounds__(SB) k_csr_vector(i64 nrows, const i32 *__restr
 #pragma unroll
             for (int u = 0; u < CU; u++) {
                 const i64 e = base + (i64)u * W;
-                cc[u] = *(e < c ? col + e : sentinel_ptr<i32>());
-                v[u] = *(e < c ? val + e : zero_ptr<V>());
+                cc[u] = load_val<NT>(e < c ? col + e : sentinel_ptr<i32>());
+                v[u] = load_val<NT>(e < c ? val + e : zero_ptr<V>());
             }
 #pragma unroll
             for (int u = 0; u < CU; u++) xv[u] = *(cc[u] >= 0 ? x + cc[u] : zero_ptr<X>());
@@ -788,26 +788,26 @@ static void coo_launch(dsm_matrix m, i64 nnz, const i32 *row, const i32 *col, co
     }
 }
 
-template <class V, class X, bool ACC>
-static void csr_launch(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s,
-                       const int *stop) {
+template <class V, class X, bool ACC, bool NT>
+static void csr_launch_nt(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s,
+                          const int *stop) {
     const i64 n = m->nrows;
     if (n == 0) return;
     const V *val = (const V *)P.val;
     if (variant == 0 || variant >= 7) {
         if (P.nrblocks == 0) return;
         if (variant == 0)
-            DSM_LAUNCH((k_csr_adaptive<V, X, ACC, true>), dim3((unsigned)P.nrblocks), dim3(SB), 0, s,
+            DSM_LAUNCH((k_csr_adaptive<V, X, ACC, true, NT>), dim3((unsigned)P.nrblocks), dim3(SB), 0, s,
                                P.rblocks, P.rp, P.col, val, x, y, stop);
         else
-            DSM_LAUNCH((k_csr_adaptive<V, X, ACC, false>), dim3((unsigned)P.nrblocks), dim3(SB), 0, s,
+            DSM_LAUNCH((k_csr_adaptive<V, X, ACC, false, NT>), dim3((unsigned)P.nrblocks), dim3(SB), 0, s,
                                P.rblocks, P.rp, P.col, val, x, y, stop);
         return;
     }
     const int W = 1 << variant;  // 2 .. 64
     const unsigned g = grid_for(n * W, SB);
 #define VEC(WW) \
-    DSM_LAUNCH((k_csr_vector<V, X, WW, ACC>), dim3(g), dim3(SB), 0, s, n, P.rp, P.col, val, x, y, stop)
+    DSM_LAUNCH((k_csr_vector<V, X, WW, ACC, NT>), dim3(g), dim3(SB), 0, s, n, P.rp, P.col, val, x, y, stop)
     switch (W) {
     case 2: VEC(2); break;
     case 4: VEC(4); break;
@@ -817,6 +817,19 @@ static void csr_launch(dsm_matrix m, const Payload &P, const X *x, X *y, int var
     default: VEC(64); break;
     }
 #undef VEC
+}
+
+// CSR variants: 0 adaptive row blocks (XCD-aware order), 1-6 vector
+// kernels with 2^v lanes per row, 7 adaptive in launch order; plus 8 (bit 3):
+// column indices and values loaded nontemporally, so the single-use matrix
+// stream does not displace the x lines that later gathers hit in the L2.
+template <class V, class X, bool ACC>
+static void csr_launch(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s,
+                       const int *stop) {
+    if (variant & CSR_VARIANT_NT)
+        csr_launch_nt<V, X, ACC, true>(m, P, x, y, variant & ~CSR_VARIANT_NT, s, stop);
+    else
+        csr_launch_nt<V, X, ACC, false>(m, P, x, y, variant, s, stop);
 }
 
 // Launch geometry of a sweep variant (workgroups = partials of the dot form).

@@ -105,7 +105,7 @@ def oracle_cg(name, tol=1e-10):
 
 # the kernel variants the timed selection tries per format (csrc/select.cpp)
 _DIA_SELECT = [0, 1, 2, 4, 8, 10, 12, 16, 18, 20, 19, 21, 32, 40, 48, 56, 50, 58]
-SELECT_VARIANTS = {"csr": [0, 7, 2, 3, 4, 5, 6], "dia": _DIA_SELECT, "hdc": _DIA_SELECT, "ell": [0, 1, 2, 4, 8, 10, 12],
+SELECT_VARIANTS = {"csr": [0, 7, 8, 15, 2, 3, 4, 5, 6], "dia": _DIA_SELECT, "hdc": _DIA_SELECT, "ell": [0, 1, 2, 4, 8, 10, 12],
                    "hyb": [0, 1, 2, 4, 8, 10, 12], "coo": [0]}
 
 

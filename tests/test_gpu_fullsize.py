@@ -139,7 +139,7 @@ def test_spmv_1m_reduced_precision_values(name, vdt):
                 continue
             raise
         log(f"[spmv-1m-{vdt}] {name} {f}")
-        variants = range(8) if f == "csr" else (range(64) if f in ("dia", "hdc") else (range(16) if f in ("ell", "hyb") else [0]))
+        variants = range(16) if f == "csr" else (range(64) if f in ("dia", "hdc") else (range(16) if f in ("ell", "hyb") else [0]))
         for v in variants:
             A.variant = v
             y = A.spmv(xt).cpu().numpy()

@@ -32,7 +32,7 @@ def run_formats(name, formats=FORMATS, tol=1e-14):
                 out[f] = "infeasible"
                 continue
             raise
-        variants = range(8) if f == "csr" else (range(64) if f in ("dia", "hdc") else (range(16) if f in ("ell", "hyb") else [0]))
+        variants = range(16) if f == "csr" else (range(64) if f in ("dia", "hdc") else (range(16) if f in ("ell", "hyb") else [0]))
         for v in variants:
             A.variant = v
             y = A.spmv(xt)
@@ -176,7 +176,7 @@ def test_spmv_nonfinite_x_stays_in_its_rows(name):
             if e.status == dsm.L.E_INFEASIBLE:
                 continue
             raise
-        variants = range(8) if f == "csr" else (range(64) if f in ("dia", "hdc") else (range(16) if f in ("ell", "hyb") else [0]))
+        variants = range(16) if f == "csr" else (range(64) if f in ("dia", "hdc") else (range(16) if f in ("ell", "hyb") else [0]))
         for v in variants:
             A.variant = v
             y = A.spmv(xt).cpu().numpy()

@@ -126,6 +126,30 @@ def test_two_level_cycle_matches_dense_composition():
     assert np.max(np.abs(z - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
+def test_injected_residual_is_not_rounding_noise():
+    """The coarse points (all coordinates even) are the colour the forward
+    sweep visits last, so after the pre-smoothing sweep their neighbours have
+    moved and the injected residual is a real fraction of r.  Were they the
+    colour that sweep updates last, each would have been solved exactly
+    against its final neighbours and the injected residual would be rounding
+    noise (checked on the reversed colour order)."""
+    L, lv = levels_of(16, 2)
+    p, f2c, colour = L[0]["problem"], L[0]["f2c"], L[0]["colour"]
+    ix = np.arange(p.nrows) % 16
+    iy = (np.arange(p.nrows) // 16) % 16
+    iz = np.arange(p.nrows) // 256
+    even = (ix % 2 == 0) & (iy % 2 == 0) & (iz % 2 == 0)
+    assert np.array_equal(np.flatnonzero(even), np.sort(f2c))
+    assert np.all(colour[even] == colour.max())
+    r = inputs.uniform_vector(p.nrows, seed=14) - 0.3
+    for order, lo, hi in ((lv[0]["order"], 0.05, 1.0),
+                          (np.argsort(colour.max() - colour, kind="stable").astype(np.int32), 0.0, 1e-14)):
+        x, _ = oracle.symgs(p.row_ptr, p.col, p.val, r, np.zeros(p.nrows), order=order)
+        rc = (r - oracle.spmv_csr(p.row_ptr, p.col, p.val, x))[f2c]
+        rel = np.linalg.norm(rc) / np.linalg.norm(r[f2c])
+        assert lo <= rel <= hi, rel
+
+
 @pytest.mark.parametrize("nlev", [1, 2, 3])
 def test_preconditioner_is_symmetric_positive(nlev):
     """Symmetric smoother, prolongation = transpose of injection: M is
@@ -148,7 +172,7 @@ def test_pcg_mg_converges_fast_on_hpcg():
     assert np.max(np.abs(x - 1.0)) <= 1e-8
     _, it_cg, _, _ = oracle.cg(p.row_ptr, p.col, p.val, p.b, tol=1e-10)
     # one level (Gauss-Seidel only) already beats plain CG, the coarse
-    # correction cuts the count further (16^3: 27 -> 23 -> 16)
+    # correction cuts the count further (16^3: 27 -> 23 -> 15)
     _, it1, _, st1 = oracle.pcg_mg(lv[:1], p.b, tol=1e-10)
     assert st1 == "converged" and it < it1 < it_cg, (it, it1, it_cg)
 
