@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # csrc/spmv.hip when the counters were taken), so an entry stops applying
 # as soon as the kernel source changes.  Source: profiles/dia_spmv_hpcg104_cold.md.
 PROFILED_TRAFFIC = {
-    ("hpcg27_104", "dia", 56, "e10cc9f793e04568"): 262273843,
+    ("hpcg27_104", "dia", 56, "88a4f5c73bd42e8a"): 262267681,
 }
 
 
@@ -585,6 +585,75 @@ def spmv_leg(dsm, torch, dev, args):
     return out
 
 
+def batched_bench(dsm, ctx, torch, dev, nsys=256, small_rows=4096, seed=0x5E4E, reps=3):
+    """The batched persistent solver on the small systems of the serving
+    stream (the first `nsys` requests of at most `small_rows` rows: 27-point
+    stencils 8^3..16^3 and banded SPD systems of 1k..4k rows), tol 1e-8:
+    one dsm_cg_solve_batched call over all of them against the same solves
+    one after another through dsm_cg_solve.  Results are checked equal."""
+    import numpy as np
+    import inputs
+    log(f"[bench] batched persistent CG on {nsys} small systems")
+    reqs = inputs.serving_stream(20 * nsys, seed=seed)
+    sel = []
+    for r in reqs:
+        if r["kind"] == "hpcg27" and r["n"] ** 3 <= small_rows:
+            sel.append(inputs.hpcg27(r["n"]))
+        elif r["kind"] == "banded_spd" and r["nrows"] <= small_rows:
+            sel.append(inputs.banded_spd(r["nrows"], r["hbw"], seed=r["seed"]))
+        if len(sel) == nsys:
+            break
+    mats, bs = [], []
+    for p in sel:
+        A = dsm.Matrix.from_csr(ctx, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
+        A.select(target=1)
+        mats.append(A)
+        bs.append(torch.from_numpy(p.b).to(dev))
+    fmts = {}
+    for A in mats:
+        f = A.info()["format_name"]
+        fmts[f] = fmts.get(f, 0) + 1
+
+    # the same solution buffers every run (the sequential solver keeps a
+    # captured iteration graph per matrix and buffers after its first solve)
+    xb = [torch.zeros_like(b) for b in bs]
+    xq = [torch.zeros_like(b) for b in bs]
+
+    def batched():
+        for x in xb:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = dsm.cg_batched(mats, bs, xb, tol=1e-8)
+        return time.perf_counter() - t0, xb, res
+
+    def sequential():
+        for x in xq:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [A.cg(b, x=x, tol=1e-8)[1] for A, b, x in zip(mats, bs, xq)]
+        return time.perf_counter() - t0, xq, res
+
+    batched()
+    sequential()
+    tb = min(batched()[0] for _ in range(reps))
+    ts, xs_s, res_s = min((sequential() for _ in range(reps)), key=lambda t: t[0])
+    _, xs_b, res_b = batched()
+    iters = [r["iters"] for r in res_b]
+    worst = max(float(torch.max(torch.abs(a - b)).item()) / max(float(torch.max(torch.abs(b)).item()), 1e-300)
+                for a, b in zip(xs_b, xs_s))
+    out = {"systems": len(mats), "rows": [int(min(p.nrows for p in sel)), int(max(p.nrows for p in sel))],
+           "formats": fmts, "tol": 1e-8, "mean_iters": round(float(np.mean(iters)), 1),
+           "all_converged": all(r["status"] == "converged" for r in res_b + res_s),
+           "batched_ms": round(tb * 1e3, 3), "batched_solves_per_s": round(len(mats) / tb, 1),
+           "sequential_ms": round(ts * 1e3, 3), "sequential_solves_per_s": round(len(mats) / ts, 1),
+           "speedup": round(ts / tb, 2), "max_rel_diff_batched_vs_sequential": worst}
+    for A in mats:
+        A.close()
+    return out
+
+
 def spmv_rates(nbytes, nnz, us):
     return {"gbps": round(nbytes / (us * 1e-6) / 1e9, 1), "gflops": round(2 * nnz / (us * 1e-6) / 1e9, 1)}
 
@@ -641,13 +710,14 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the local/remote split leg")
     ap.add_argument("--no-mg", action="store_true", help="skip the multigrid-preconditioned CG leg")
     ap.add_argument("--no-small", action="store_true", help="skip the HPCG 16^3 leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched small-system leg")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--format", default=None, help="force a format instead of selecting")
     ap.add_argument("--variant", type=int, default=None, help="kernel variant with --format")
     ap.add_argument("--cold-only", action="store_true",
                     help="after the set-up, run only the cold-cache launches (for kernel traces of them)")
     ap.add_argument("--leg", default=None,
-                    choices=["cg", "pcg_mg", "ir_cg", "split", "irregular", "serving", "small", "spmv"],
+                    choices=["cg", "pcg_mg", "ir_cg", "split", "irregular", "serving", "small", "spmv", "batched"],
                     help="run only this leg (after the matrix set-up) and print its JSON; for profiling")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, run a device copy of this many MiB `steps` times "
@@ -705,7 +775,8 @@ def main():
                 "split": lambda: split_bench(dsm, ctx, torch, dev, n=args.n),
                 "irregular": lambda: irregular_bench(dsm, ctx, torch, dev),
                 "serving": lambda: serving_bench(dsm, ctx, torch, dev, nreq=args.serve_requests),
-                "small": lambda: small_bench(dsm, ctx, torch, dev)}
+                "small": lambda: small_bench(dsm, ctx, torch, dev),
+                "batched": lambda: batched_bench(dsm, ctx, torch, dev)}
         if args.leg == "cg":
             A.select(use_cache=False)
         res = strip_arrays(legs[args.leg]())
@@ -884,6 +955,7 @@ def main():
     spl = split_bench(dsm, ctx, torch, dev, n=args.n) if go and not args.no_split else None
     mgb = mg_bench(dsm, ctx, torch, dev, n=args.n) if go and not (args.no_mg or args.n % 8) else None
     serve = serving_bench(dsm, ctx, torch, dev, nreq=args.serve_requests) if go and not args.no_serve else None
+    bat = batched_bench(dsm, ctx, torch, dev) if go and not args.no_batched else None
     spmv_src = os.path.join(ROOT, "paper_2209_06478_amd", "csrc", "spmv.hip")
     traffic = PROFILED_TRAFFIC.get((f"hpcg27_{args.n}", cfmt, cvar, source_digest(spmv_src)))
     out = {
@@ -941,6 +1013,7 @@ def main():
         "split": spl,
         "pcg_mg": mgb,
         "serving": serve,
+        "batched_small_systems": bat,
         "cpu_baseline": cpu_baseline_line(cpu_res, args.n) if cpu_res else None,
         "paper_context": {"note": "ratios the paper reports on other hardware; context, not targets",
                           "format_selection_gain": "up to 2.5x on CPU (ARCHER2, 2x AMD EPYC 7742) and up to 7x "

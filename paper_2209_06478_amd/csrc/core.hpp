@@ -181,9 +181,10 @@ void spmv(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int v
 // diag.hip: mode 0 extracts A(i, i) into d (FP64, 0 where absent); mode 1
 // writes d into the diagonal entries the structure holds (blocking).
 void diagonal_op(dsm_matrix m, double *d, int mode, hipStream_t s);
-// Square DIA/ELL only: y = A x plus, per workgroup, the partial of x . y in
-// part[]; *count (when given) is incremented once per launch.  Returns the
-// number of partials written, or 0 (nothing launched) for other payloads.
+// Square DIA/ELL (and HDC/HYB whose CSR/COO part is empty) only: y = A x
+// plus, per workgroup, the partial of x . y in part[]; *count (when given)
+// is incremented once per launch.  Returns the number of partials written,
+// or 0 (nothing launched) for other payloads.
 int spmv_dot(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant, hipStream_t s,
              double *part, long long *count, const int *stop);
 // Algorithmic bytes one SpMV must move (x read once, y written once).

@@ -974,7 +974,11 @@ static int spmv_dot_typed(dsm_matrix m, const Payload &P, const X *x, X *y, int 
 
 int spmv_dot(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant, hipStream_t s,
              double *part, long long *count, const int *stop) {
-    if (!(P.fmt == DSM_DIA || P.fmt == DSM_ELL) || m->nrows != m->ncols || m->nrows == 0) return 0;
+    // HDC whose CSR part is empty and HYB whose COO part is empty are one
+    // DIA or ELL sweep, which writes y alone and can carry the epilogue
+    const bool one_sweep = P.fmt == DSM_DIA || P.fmt == DSM_ELL || (P.fmt == DSM_HDC && P.csr_nnz == 0) ||
+                           (P.fmt == DSM_HYB && P.coo_nnz == 0);
+    if (!one_sweep || m->nrows != m->ncols || m->nrows == 0) return 0;
     if (vdt == DSM_F64)
         return spmv_dot_typed<double>(m, P, (const double *)x, (double *)y, variant, s, part, count, stop);
     return spmv_dot_typed<float>(m, P, (const float *)x, (float *)y, variant, s, part, count, stop);
