@@ -520,7 +520,14 @@ typedef struct dsm_mg_s *dsm_mg;
  * updates one colour at a time, ascending forward and descending backward,
  * which equals a sequential Gauss-Seidel sweep over rows in (colour, row)
  * order.  Invalid structure (ranges, coupled colours, zero diagonal) gives
- * DSM_E_INVALID; other formats or dtypes DSM_E_UNSUPPORTED.  Blocking. */
+ * DSM_E_INVALID; other formats or dtypes DSM_E_UNSUPPORTED.  Blocking.
+ * DIA levels keep a colour-ordered copy of their diagonals (the level's
+ * value bytes again); 7- and 27-diagonal levels whose colours have at most
+ * 512 rows also keep a record of (diagonals + 1) x 8 bytes per row and sweep in
+ * one workgroup with x in LDS.  Two environment switches pick equivalent
+ * executions (same results), for timing one against the other:
+ * DSM_MG_LDS=0 (small levels sweep through the L2 instead of LDS) and
+ * DSM_MG_ND=0 (the runtime-length colour sweep for 7/27 diagonals). */
 dsm_status dsm_mg_create(dsm_ctx ctx, int32_t nlevels, const dsm_matrix *levels, const int32_t *const *f2c,
                          const int32_t *const *colour, void *stream, dsm_mg *out);
 

@@ -47,8 +47,22 @@ def rel_err(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
+@functools.lru_cache(maxsize=None)
+def seven_point_hierarchy(n, nlev):
+    """The HPCG grids, colourings and coarse maps with the anisotropic
+    7-point operator on every level (7 diagonals: the 7-diagonal forms of
+    the DIA smoother)."""
+    out = []
+    for lv in inputs.hpcg27_levels(n, nlev):
+        m = round(lv["problem"].nrows ** (1 / 3))
+        d = dict(lv)
+        d["problem"] = inputs.aniso7(m)
+        out.append(d)
+    return out
+
+
 @pytest.mark.parametrize("fmt", ["csr", "dia"])
-@pytest.mark.parametrize("n", [2, 5, 16])
+@pytest.mark.parametrize("n", [2, 5, 16, 24])
 def test_symgs_matches_oracle(fmt, n):
     torch, dev = torch_dev()
     L = hierarchy(n, 1)
@@ -64,6 +78,32 @@ def test_symgs_matches_oracle(fmt, n):
     err = rel_err(x.cpu().numpy(), xr)
     log(f"[mg] symgs {fmt} {n}^3 err {err:.2e}")
     assert err <= 1e-12
+    if fmt == "dia":
+        # same products, same order, no fused multiply-add: the same bits
+        assert np.array_equal(x.cpu().numpy(), xr)
+    mg.close()
+
+
+@pytest.mark.parametrize("n,nlev", [(8, 1), (24, 1), (24, 2)])
+def test_seven_point_levels_match_oracle(n, nlev):
+    """7-diagonal DIA levels: the LDS sweep (8^3, 12^3) and the per-colour
+    launches (24^3), one sweep and one V-cycle, bit for bit."""
+    torch, dev = torch_dev()
+    L = seven_point_hierarchy(n, nlev)
+    mg, mats = build(L, "dia")
+    p = L[0]["problem"]
+    r = inputs.uniform_vector(p.nrows, seed=24) - 0.4
+    x0 = inputs.uniform_vector(p.nrows, seed=25)
+    xr, bad = oracle.symgs(p.row_ptr, p.col, p.val, r, x0, order=oracle_levels(L)[0]["order"])
+    assert bad == 0
+    x = torch.from_numpy(x0).to(dev)
+    mg.symgs(0, torch.from_numpy(r).to(dev), x)
+    assert np.array_equal(x.cpu().numpy(), xr)
+    zr = oracle.mg(oracle_levels(L), r)
+    z = mg.apply(torch.from_numpy(r).to(dev))
+    err = rel_err(z.cpu().numpy(), zr)
+    log(f"[mg] seven-point {n}^3 x{nlev} vcycle err {err:.2e}")
+    assert np.array_equal(z.cpu().numpy(), zr)
     mg.close()
 
 
@@ -80,6 +120,8 @@ def test_vcycle_matches_oracle(fmt, n, nlev):
     err = rel_err(z.cpu().numpy(), zr)
     log(f"[mg] vcycle {fmt} {n}^3 x{nlev} err {err:.2e}")
     assert err <= 1e-12
+    if fmt == "dia":
+        assert np.array_equal(z.cpu().numpy(), zr)
     # a second application reuses the coarse vectors: same bits
     z2 = mg.apply(torch.from_numpy(r).to(dev))
     torch.cuda.synchronize()
