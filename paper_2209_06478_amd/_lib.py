@@ -141,6 +141,12 @@ def load(path=None):
     if not os.path.exists(path):
         raise RuntimeError(f"libdsm.so not found at {path}: build it with paper_2209_06478_amd/build.py "
                            "(there is no CPU fallback)")
+    # torch first: its wheel carries its own HIP runtime under the same
+    # soname (libamdhip64.so.7) as the system one libdsm was linked against,
+    # and the first one loaded serves the process.  Device memory and
+    # streams come from torch, so libdsm must run on torch's runtime; loaded
+    # the other way round, torch's runtime finds no GPU.
+    import torch  # noqa: F401
     L = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(L, name)
