@@ -629,8 +629,10 @@ __global__ void __launch_bounds__(CGB) k_pcg_update_p(i64 n, const double *r, do
 // ================================================================ host side
 struct CgBuffers {
     // FP64 part (p2: second p buffer of the fused iteration; dinv: inverse
-    // diagonal of the Jacobi preconditioner)
+    // diagonal of the Jacobi preconditioner; xw: the iterate of the
+    // graph-replayed FP64 loop)
     double *r = nullptr, *p = nullptr, *q = nullptr, *p2 = nullptr, *dinv = nullptr, *part_c = nullptr;
+    double *xw = nullptr;
     double *part_a = nullptr, *part_b = nullptr, *norms = nullptr;
     CgState *st = nullptr, *st2 = nullptr;
     // FP32 inner part (IR)
@@ -646,7 +648,7 @@ static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 // Workspace bytes a solve of this matrix needs (also used for admission).
 size_t cg_workspace_bytes(i64 n, bool ir) {
     const size_t nn = (size_t)std::max<i64>(n, 1);
-    size_t bytes = 5 * round256(nn * 8) + 3 * round256(partial_slots(n) * 8) + 8 * 256;
+    size_t bytes = 6 * round256(nn * 8) + 3 * round256(partial_slots(n) * 8) + 8 * 256;
     if (ir) bytes += 6 * round256(nn * 4);
     return bytes;
 }
@@ -668,6 +670,7 @@ static CgBuffers cg_buffers(dsm_matrix m, bool ir, Workspace &cgws, hipStream_t 
     B.part_b = (double *)take(partial_slots(m->nrows) * 8);
     B.part_c = (double *)take(partial_slots(m->nrows) * 8);
     B.dinv = (double *)take(n * 8);
+    B.xw = (double *)take(n * 8);
     B.norms = (double *)take(64);
     B.st = (CgState *)take(sizeof(CgState));
     B.st2 = (CgState *)take(sizeof(CgState));
@@ -877,9 +880,16 @@ void cg_solve_ws(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o,
         return;
     }
     if (!ir) {
-        CgState h = run_cg<double>(m, b, x, B.r, B.p, B.q, B.p2, B.part_a, B.part_b, B.st, DSM_F64, o.tol, maxit,
-                                   every, s,
-                                   spws, cgws, use_graph);
+        // The graph-replayed loop iterates on a workspace copy of x, copied
+        // back at the end: the captured graph then holds only workspace
+        // buffers and stays valid from solve to solve, whatever x the caller
+        // passes (with the caller's x in it, a new x meant a new capture).
+        const bool graphed = use_graph && cg_graphs_enabled();
+        double *xi = graphed ? B.xw : x;
+        if (graphed) DSM_HIP(hipMemcpyAsync(xi, x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
+        CgState h = run_cg<double>(m, b, xi, B.r, B.p, B.q, B.p2, B.part_a, B.part_b, B.st, DSM_F64, o.tol, maxit,
+                                   every, s, spws, cgws, use_graph);
+        if (graphed) DSM_HIP(hipMemcpyAsync(x, xi, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
         R.iters = h.iters;
         R.relres = h.relres;
         R.status = h.done == 1 ? DSM_OK : h.done == 3 ? DSM_E_BREAKDOWN : DSM_E_NOT_CONVERGED;

@@ -63,8 +63,8 @@ struct dsm_mg_s {
     dsm_ctx ctx = nullptr;
     std::vector<Level> L;
     std::vector<std::pair<void *, size_t>> bufs;
-    // PCG vectors and state
-    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+    // PCG vectors and state (xw: the iterate of the graph-replayed loop)
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *xw = nullptr;
     double *part_a = nullptr, *part_b = nullptr, *part_c = nullptr;
     dsm::CgState *st = nullptr;
     dsm::Workspace gws;
@@ -920,6 +920,12 @@ static CgState run_pcg_mg(dsm_mg_s *mg, const double *b, double *x, double tol, 
     hipLaunchKernelGGL(k_pmg_init_state, dim3(1), dim3(CGB), 0, s, mg->part_b, st, tol, maxit);
     DSM_HIP(hipGetLastError());
     const int *stop = &st->done;
+    // the replayed chunks update a copy of x the hierarchy owns (copied back
+    // below), so the captured graph holds no caller buffer and serves every
+    // solve whatever x is passed
+    const bool graphed = cg_graphs_enabled();
+    double *xi = graphed ? mg->xw : x;
+    if (graphed) DSM_HIP(hipMemcpyAsync(xi, x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
     auto enqueue = [&](int, hipStream_t ss) {
         vcycle(mg, 0, mg->r, mg->z, ss, stop);
         hipLaunchKernelGGL(k_pmg_rz, dim3(CGG), dim3(CGB), 0, ss, n, mg->r, mg->z, mg->part_c, st);
@@ -930,14 +936,16 @@ static CgState run_pcg_mg(dsm_mg_s *mg, const double *b, double *x, double tol, 
             hipLaunchKernelGGL(k_pmg_dot_pq<double>, dim3(CGG), dim3(CGB), 0, ss, n, mg->p, mg->q, mg->part_a, st);
             npq = CGG;
         }
-        hipLaunchKernelGGL(k_pmg_update_xr, dim3(CGG), dim3(CGB), 0, ss, n, x, mg->r, mg->p, mg->q, mg->part_a,
+        hipLaunchKernelGGL(k_pmg_update_xr, dim3(CGG), dim3(CGB), 0, ss, n, xi, mg->r, mg->p, mg->q, mg->part_a,
                            npq, mg->part_b, st);
         hipLaunchKernelGGL(k_pmg_check, dim3(1), dim3(CGB), 0, ss, mg->part_b, st);
         DSM_HIP(hipGetLastError());
     };
     char key[256];
-    snprintf(key, sizeof key, "pmg|%p|%p|%p|%d|%d", (void *)b, (void *)x, (void *)mg, A->variant, every);
-    return run_chunks(mg->gws, key, true, every, maxit, st, s, enqueue);
+    snprintf(key, sizeof key, "pmg|%p|%p|%d|%d", (void *)mg, (void *)xi, A->variant, every);
+    const CgState h = run_chunks(mg->gws, key, true, every, maxit, st, s, enqueue);
+    if (graphed) DSM_HIP(hipMemcpyAsync(x, xi, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    return h;
 }
 
 }  // namespace dsm
@@ -976,6 +984,7 @@ DSM_API dsm_status dsm_mg_create(dsm_ctx ctx, int32_t nlevels, const dsm_matrix 
             mg->z = (double *)mg->alloc(nb);
             mg->p = (double *)mg->alloc(nb);
             mg->q = (double *)mg->alloc(nb);
+            mg->xw = (double *)mg->alloc(nb);
             mg->part_a = (double *)mg->alloc(sizeof(double) * pcg_partials(n));
             mg->part_b = (double *)mg->alloc(sizeof(double) * pcg_partials(n));
             mg->part_c = (double *)mg->alloc(sizeof(double) * pcg_partials(n));

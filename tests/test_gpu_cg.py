@@ -111,13 +111,16 @@ def test_cg_nonzero_initial_guess():
     A.close()
 
 
+@pytest.mark.parametrize("graph", ["1", "0"])
 @pytest.mark.parametrize("offset", [0, 1])
-def test_cg_ragged_sizes_and_unaligned_x(offset):
+def test_cg_ragged_sizes_and_unaligned_x(offset, graph, monkeypatch):
     """The FP64 vector updates load two elements per lane where every vector
     is 16-byte aligned: odd sizes end them with a ragged tail, and an x that
     starts 8 bytes past a 16-byte boundary (offset 1) takes one element per
-    load.  IR on the same systems covers its FP32 inner loop at odd sizes."""
+    load (eager launches; the replayed loop works on an aligned copy of x).
+    IR on the same systems covers its FP32 inner loop at odd sizes."""
     torch, dev = torch_dev()
+    monkeypatch.setenv("DSM_CG_GRAPH", graph)
     for p in [inputs.hpcg27(7), inputs.banded_spd(1203, 5, seed=4), inputs.hpcg27(1)]:
         n = p.nrows
         xo, it, rr, st = oracle.cg(p.row_ptr, p.col, p.val, p.b, tol=1e-10)
