@@ -641,7 +641,8 @@ struct CgBuffers {
 
 // Partials per workgroup: the vector kernels use CGG, the fused SpMV one per
 // 256-row tile.
-static size_t partial_slots(i64 n) { return (size_t)std::max<i64>(CGG, n / 256 + 2); }
+static size_t partial_slots(i64 n) { return (size_t)dot_partials_cap(n); }
+static_assert(CGG <= 512, "the vector kernels' partials must fit dot_partials_cap");
 
 static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -692,9 +693,9 @@ static CgBuffers cg_buffers(dsm_matrix m, bool ir, Workspace &cgws, hipStream_t 
 // vector kernels 40% of all kernel time).
 static unsigned vec_grid(i64 n) { return (unsigned)std::max<i64>(1, std::min<i64>(CGG, (n + CGB - 1) / CGB)); }
 
-// One CG iteration: SpMV with p.q, x/r update, p update (DIA/ELL sweeps
-// write the p.q partials themselves; other formats take a separate dot
-// kernel).  Every kernel checks the state's done flag first, so iterations
+// One CG iteration: SpMV with p.q, x/r update, p update (DIA/ELL sweeps and
+// CSR launches of at most dot_partials_cap(n) workgroups write the p.q
+// partials themselves; the rest take a separate dot kernel).  Every kernel checks the state's done flag first, so iterations
 // enqueued past convergence cost only their launches.
 template <class X>
 static void enqueue_iteration(dsm_matrix m, X *x, X *r, X *p, X *q, double *part_a, double *part_b, CgState *st,

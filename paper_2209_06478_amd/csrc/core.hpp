@@ -181,10 +181,15 @@ void spmv(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int v
 // diag.hip: mode 0 extracts A(i, i) into d (FP64, 0 where absent); mode 1
 // writes d into the diagonal entries the structure holds (blocking).
 void diagonal_op(dsm_matrix m, double *d, int mode, hipStream_t s);
-// Square DIA/ELL (and HDC/HYB whose CSR/COO part is empty) only: y = A x
-// plus, per workgroup, the partial of x . y in part[]; *count (when given)
-// is incremented once per launch.  Returns the number of partials written,
-// or 0 (nothing launched) for other payloads.
+// Partial slots the solvers allocate per dot product (at least the 512 of
+// their vector kernels; one per 256-row tile of a sweep): spmv_dot writes at
+// most this many.
+inline i64 dot_partials_cap(i64 n) { return n / 256 + 2 > 512 ? n / 256 + 2 : 512; }
+// Square DIA/ELL (and HDC/HYB whose CSR/COO part is empty), and square CSR
+// when its launch has at most dot_partials_cap(n) workgroups: y = A x plus,
+// per workgroup, the partial of x . y in part[]; *count (when given) is
+// incremented once per launch.  Returns the number of partials written, or
+// 0 (nothing launched) for other payloads.
 int spmv_dot(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int variant, hipStream_t s,
              double *part, long long *count, const int *stop);
 // Algorithmic bytes one SpMV must move (x read once, y written once).

@@ -952,7 +952,7 @@ static CgState run_pcg_mg(dsm_mg_s *mg, const double *b, double *x, double tol, 
 
 using namespace dsm;
 
-static size_t pcg_partials(int64_t n) { return (size_t)std::max<int64_t>(CGG, n / 256 + 2); }
+static size_t pcg_partials(int64_t n) { return (size_t)dot_partials_cap(n); }
 
 DSM_API dsm_status dsm_mg_create(dsm_ctx ctx, int32_t nlevels, const dsm_matrix *levels, const int32_t *const *f2c,
                                  const int32_t *const *colour, void *stream, dsm_mg *out) {

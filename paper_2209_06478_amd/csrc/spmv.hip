@@ -105,11 +105,16 @@ __device__ __forceinline__ void store_y(X *y, i64 i, X v, bool acc) {
 }
 
 // ---------------------------------------------------------------- CSR
-template <class V, class X, bool ACC, bool XCD, bool NT = false>
+// DOT (square matrices inside CG): the workgroup also writes its partial of
+// x . y over the rows it owns, in FP64, to part[blockIdx.x] (workgroup 0
+// counts the launch), as the DIA/ELL sweeps do; every thread of a
+// workgroup reaches its reduction.
+template <class V, class X, bool ACC, bool XCD, bool NT = false, bool DOT = false>
 __global__ void __launch_bounds__(SB) k_csr_adaptive(const i32 *__restrict__ blocks, const i32 *__restrict__ rp,
                                                      const i32 *__restrict__ col, const V *__restrict__ val,
                                                      const X *__restrict__ x, X *__restrict__ y,
-                                                     const int *__restrict__ stop) {
+                                                     const int *__restrict__ stop, double *__restrict__ part = nullptr,
+                                                     long long *count = nullptr) {
     __shared__ int s_stop;
     if (threadIdx.x == 0) s_stop = stop ? *stop : 0;
     __syncthreads();
@@ -141,7 +146,13 @@ __global__ void __launch_bounds__(SB) k_csr_adaptive(const i32 *__restrict__ blo
             for (int u = 0; u < CU; u++) s += widen<X>(v[u]) * xv[u];
         }
         s = block_sum(s, red);
-        if (tid == 0) store_y(y, r0, s, ACC);
+        if (tid == 0) {
+            store_y(y, r0, s, ACC);
+            if constexpr (DOT) {
+                part[blockIdx.x] = (double)x[r0] * (double)s;
+                if (count && blockIdx.x == 0) *count += 1;
+            }
+        }
         return;
     }
     {
@@ -180,12 +191,22 @@ __global__ void __launch_bounds__(SB) k_csr_adaptive(const i32 *__restrict__ blo
     }
     for (int off = L >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, WAVE);
     if (rl < nr && lane == 0) store_y(y, r0 + rl, s, ACC);
+    if constexpr (DOT) {
+        __shared__ double dred[SB / WAVE];
+        double d = rl < nr && lane == 0 ? (double)x[r0 + rl] * (double)s : 0.0;
+        d = block_sum(d, dred);
+        if (tid == 0) {
+            part[blockIdx.x] = d;
+            if (count && blockIdx.x == 0) *count += 1;
+        }
+    }
 }
 
-template <class V, class X, int W, bool ACC, bool NT = false>
+template <class V, class X, int W, bool ACC, bool NT = false, bool DOT = false>
 __global__ void __launch_bounds__(SB) k_csr_vector(i64 nrows, const i32 *__restrict__ rp, const i32 *__restrict__ col,
                                                    const V *__restrict__ val, const X *__restrict__ x,
-                                                   X *__restrict__ y, const int *__restrict__ stop) {
+                                                   X *__restrict__ y, const int *__restrict__ stop,
+                                                   double *__restrict__ part = nullptr, long long *count = nullptr) {
     if (stop && *stop) return;
     // launch order, not the XCD-aware order: with it the HPCG 104^3 launch
     // fetched 382 instead of 456 MB (no x lines fetched into several L2s)
@@ -213,6 +234,15 @@ __global__ void __launch_bounds__(SB) k_csr_vector(i64 nrows, const i32 *__restr
     }
     s = group_sum<W>(s);
     if (row < nrows && lane == 0) store_y(y, row, s, ACC);
+    if constexpr (DOT) {
+        __shared__ double dred[SB / WAVE];
+        double d = row < nrows && lane == 0 ? (double)x[row] * (double)s : 0.0;
+        d = block_sum(d, dred);
+        if (threadIdx.x == 0) {
+            part[blockIdx.x] = d;
+            if (count && blockIdx.x == 0) *count += 1;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- DIA / ELL
@@ -788,26 +818,28 @@ static void coo_launch(dsm_matrix m, i64 nnz, const i32 *row, const i32 *col, co
     }
 }
 
-template <class V, class X, bool ACC, bool NT>
-static void csr_launch_nt(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s,
-                          const int *stop) {
+// CSR launches; returns the number of workgroups (= partials with DOT).
+template <class V, class X, bool ACC, bool NT, bool DOT = false>
+static unsigned csr_launch_nt(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s,
+                              const int *stop, double *part = nullptr, long long *count = nullptr) {
     const i64 n = m->nrows;
-    if (n == 0) return;
+    if (n == 0) return 0;
     const V *val = (const V *)P.val;
     if (variant == 0 || variant >= 7) {
-        if (P.nrblocks == 0) return;
+        if (P.nrblocks == 0) return 0;
         if (variant == 0)
-            DSM_LAUNCH((k_csr_adaptive<V, X, ACC, true, NT>), dim3((unsigned)P.nrblocks), dim3(SB), 0, s,
-                               P.rblocks, P.rp, P.col, val, x, y, stop);
+            DSM_LAUNCH((k_csr_adaptive<V, X, ACC, true, NT, DOT>), dim3((unsigned)P.nrblocks), dim3(SB), 0, s,
+                       P.rblocks, P.rp, P.col, val, x, y, stop, part, count);
         else
-            DSM_LAUNCH((k_csr_adaptive<V, X, ACC, false, NT>), dim3((unsigned)P.nrblocks), dim3(SB), 0, s,
-                               P.rblocks, P.rp, P.col, val, x, y, stop);
-        return;
+            DSM_LAUNCH((k_csr_adaptive<V, X, ACC, false, NT, DOT>), dim3((unsigned)P.nrblocks), dim3(SB), 0, s,
+                       P.rblocks, P.rp, P.col, val, x, y, stop, part, count);
+        return (unsigned)P.nrblocks;
     }
     const int W = 1 << variant;  // 2 .. 64
     const unsigned g = grid_for(n * W, SB);
-#define VEC(WW) \
-    DSM_LAUNCH((k_csr_vector<V, X, WW, ACC, NT>), dim3(g), dim3(SB), 0, s, n, P.rp, P.col, val, x, y, stop)
+#define VEC(WW)                                                                                                \
+    DSM_LAUNCH((k_csr_vector<V, X, WW, ACC, NT, DOT>), dim3(g), dim3(SB), 0, s, n, P.rp, P.col, val, x, y, stop, \
+               part, count)
     switch (W) {
     case 2: VEC(2); break;
     case 4: VEC(4); break;
@@ -817,19 +849,26 @@ static void csr_launch_nt(dsm_matrix m, const Payload &P, const X *x, X *y, int 
     default: VEC(64); break;
     }
 #undef VEC
+    return g;
+}
+
+// Workgroups (= partials) a CSR launch of this variant runs.
+static i64 csr_groups(dsm_matrix m, const Payload &P, int variant) {
+    const int v = variant & ~CSR_VARIANT_NT;
+    if (v == 0 || v >= 7) return P.nrblocks;
+    return grid_for(m->nrows * (1 << v), SB);
 }
 
 // CSR variants: 0 adaptive row blocks (XCD-aware order), 1-6 vector
 // kernels with 2^v lanes per row, 7 adaptive in launch order; plus 8 (bit 3):
 // column indices and values loaded nontemporally, so the single-use matrix
 // stream does not displace the x lines that later gathers hit in the L2.
-template <class V, class X, bool ACC>
-static void csr_launch(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s,
-                       const int *stop) {
+template <class V, class X, bool ACC, bool DOT = false>
+static unsigned csr_launch(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s,
+                           const int *stop, double *part = nullptr, long long *count = nullptr) {
     if (variant & CSR_VARIANT_NT)
-        csr_launch_nt<V, X, ACC, true>(m, P, x, y, variant & ~CSR_VARIANT_NT, s, stop);
-    else
-        csr_launch_nt<V, X, ACC, false>(m, P, x, y, variant, s, stop);
+        return csr_launch_nt<V, X, ACC, true, DOT>(m, P, x, y, variant & ~CSR_VARIANT_NT, s, stop, part, count);
+    return csr_launch_nt<V, X, ACC, false, DOT>(m, P, x, y, variant, s, stop, part, count);
 }
 
 // Launch geometry of a sweep variant (workgroups = partials of the dot form).
@@ -963,6 +1002,13 @@ void spmv(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, int v
 template <class X>
 static int spmv_dot_typed(dsm_matrix m, const Payload &P, const X *x, X *y, int variant, hipStream_t s,
                           double *part, long long *count, const int *stop) {
+    if (P.fmt == DSM_CSR) {
+        switch (P.vdt) {
+        case DSM_F64: return (int)csr_launch<double, X, false, true>(m, P, x, y, variant, s, stop, part, count);
+        case DSM_F32: return (int)csr_launch<float, X, false, true>(m, P, x, y, variant, s, stop, part, count);
+        default: return (int)csr_launch<bf16, X, false, true>(m, P, x, y, variant, s, stop, part, count);
+        }
+    }
     switch (P.vdt) {
     case DSM_F64: sweep<double, X, false, true>(m, P, x, y, variant, s, stop, part, count); break;
     case DSM_F32: sweep<float, X, false, true>(m, P, x, y, variant, s, stop, part, count); break;
@@ -978,7 +1024,11 @@ int spmv_dot(dsm_matrix m, const Payload &P, const void *x, void *y, int vdt, in
     // DIA or ELL sweep, which writes y alone and can carry the epilogue
     const bool one_sweep = P.fmt == DSM_DIA || P.fmt == DSM_ELL || (P.fmt == DSM_HDC && P.csr_nnz == 0) ||
                            (P.fmt == DSM_HYB && P.coo_nnz == 0);
-    if (!one_sweep || m->nrows != m->ncols || m->nrows == 0) return 0;
+    // CSR: when its workgroups fit the solvers' partial buffers (the
+    // adaptive kernel runs a workgroup per row block: about nnz/1024 of them)
+    const bool csr = P.fmt == DSM_CSR && csr_groups(m, P, variant) <= dot_partials_cap(m->nrows) &&
+                     csr_groups(m, P, variant) > 0;
+    if (!(one_sweep || csr) || m->nrows != m->ncols || m->nrows == 0) return 0;
     if (vdt == DSM_F64)
         return spmv_dot_typed<double>(m, P, (const double *)x, (double *)y, variant, s, part, count, stop);
     return spmv_dot_typed<float>(m, P, (const float *)x, (float *)y, variant, s, part, count, stop);

@@ -37,11 +37,14 @@ def test_cg_hpcg16_every_format(fmt):
     assert np.linalg.norm(x - xo) <= 10 * KAPPA[16] * 1e-10 * np.linalg.norm(xo)
 
 
-@pytest.mark.parametrize("fmt,variant", [("dia", v) for v in (0, 2, 8, 13, 16, 19, 21, 31)] + [("hdc", 18), ("ell", 10)])
+@pytest.mark.parametrize("fmt,variant", [("dia", v) for v in (0, 2, 8, 13, 16, 19, 21, 31)] + [("hdc", 18), ("ell", 10)]
+                         + [("csr", v) for v in (0, 7, 2, 6, 8, 15)])
 def test_cg_sweep_variants(fmt, variant):
-    """The three-kernel loop with the sweep's p.q epilogue in every kind of
+    """The three-kernel loop with the SpMV's p.q epilogue in every kind of
     sweep (gathered x, paired rows, LDS-staged x with 1, 2 and 4 row groups,
-    both tile orders) reaches the oracle's iterate."""
+    both tile orders) and every kind of CSR launch (adaptive row blocks in
+    both orders, 4- and 64-lane rows, nontemporal loads) reaches the
+    oracle's iterate."""
     torch, dev = torch_dev()
     p = problem("hpcg16")
     xo, it, rr, st = oracle.cg(p.row_ptr, p.col, p.val, p.b, tol=1e-10)
