@@ -84,6 +84,30 @@ def test_symgs_matches_oracle(fmt, n):
     mg.close()
 
 
+@pytest.mark.parametrize("n", [5, 24])
+def test_symgs_non_lattice_colouring(n):
+    """A valid 12-colouring other than the grid's parity colouring (x
+    coordinate mod 3, y and z parities): the DIA sweep follows any colour
+    order, bit for bit the oracle's sweep in that order."""
+    torch, dev = torch_dev()
+    p = inputs.hpcg27(n)
+    i = np.arange(p.nrows)
+    ix, iy, iz = i % n, (i // n) % n, i // (n * n)
+    colour = ((ix % 3) + 3 * ((iy & 1) + 2 * (iz & 1))).astype(np.int32)
+    A = dsm.Matrix.from_csr(ctx(), p.nrows, p.ncols, p.row_ptr, p.col, p.val)
+    A.convert("dia")
+    mg = dsm.Multigrid(ctx(), [A], [], [colour])
+    r = inputs.uniform_vector(p.nrows, seed=31) - 0.5
+    x0 = inputs.uniform_vector(p.nrows, seed=32)
+    xr, bad = oracle.symgs(p.row_ptr, p.col, p.val, r, x0, order=np.argsort(colour, kind="stable").astype(np.int32))
+    assert bad == 0
+    x = torch.from_numpy(x0).to(dev)
+    mg.symgs(0, torch.from_numpy(r).to(dev), x)
+    log(f"[mg] symgs 12 colours {n}^3")
+    assert np.array_equal(x.cpu().numpy(), xr)
+    mg.close()
+
+
 @pytest.mark.parametrize("n,nlev", [(8, 1), (24, 1), (24, 2)])
 def test_seven_point_levels_match_oracle(n, nlev):
     """7-diagonal DIA levels: the LDS sweep (8^3, 12^3) and the per-colour
