@@ -59,10 +59,11 @@ def alg_bytes(info, N, nnz, v=8, X=8):
     }[info["format_name"]]
 
 
-def cg_leg(A, p, torch, dev, solves):
+def cg_leg(A, p, torch, dev, solves, mode="f64"):
     """CG to 1e-10 on the matrix in its current format: solves/s, p50/p99
     latency and time per iteration (the first solve, which captures the
-    iteration graph, is not counted)."""
+    iteration graph, is not counted).  mode "jacobi": CG preconditioned
+    with the matrix diagonal."""
     import numpy as np
     b = torch.from_numpy(p.b).to(dev)
     lat = []
@@ -71,17 +72,19 @@ def cg_leg(A, p, torch, dev, solves):
         xs = torch.zeros(p.nrows, dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        xs, res = A.cg(b, x=xs, tol=1e-10)
+        xs, res = A.cg(b, x=xs, tol=1e-10, mode=mode)
         lat.append((time.perf_counter() - t1) * 1e3)
     lat = np.array(lat[1:])
     info = A.info()
     N = p.nrows
     # per iteration: one SpMV (the format's bytes) plus the vector kernels:
     # update x, r (read x, p, r, q; write x, r) and p (read r, p; write p)
-    # = 80 N bytes, and 16 N more for a separate p.q kernel (not DIA/ELL)
-    vec = 80 * N + (0 if info["format_name"] in ("dia", "ell") else 16 * N)
+    # = 80 N bytes (Jacobi: the inverse diagonal read in both, 96 N), and
+    # 16 N more for a separate p.q kernel (formats whose SpMV does not write
+    # the p.q partials)
+    vec = (96 if mode == "jacobi" else 80) * N + (0 if info["format_name"] in ("dia", "ell") else 16 * N)
     it_bytes = alg_bytes(info, N, p.nnz) + vec
-    return {"format": info["format_name"], "variant": A.variant, "tol": 1e-10, "iters": res["iters"],
+    return {"mode": mode, "format": info["format_name"], "variant": A.variant, "tol": 1e-10, "iters": res["iters"],
             "bytes_per_iter": int(it_bytes),
             "effective_gbps": round(it_bytes / (float(lat.mean()) * 1e-3 / max(res["iters"], 1)) / 1e9, 1),
             "status": res["status"], "relres_true": res["relres_true"],
@@ -769,7 +772,8 @@ def main():
         A.spmv(x, out=y)
 
     if args.leg:
-        legs = {"cg": lambda: cg_leg(A, p, torch, dev, args.cg_solves),
+        legs = {"cg": lambda: dict(cg_leg(A, p, torch, dev, args.cg_solves),
+                                   jacobi=cg_leg(A, p, torch, dev, max(3, args.cg_solves // 4), mode="jacobi")),
                 "pcg_mg": lambda: mg_bench(dsm, ctx, torch, dev, n=args.n),
                 "ir_cg": lambda: ir_bench(dsm, ctx, torch, dev),
                 "split": lambda: split_bench(dsm, ctx, torch, dev, n=args.n),
@@ -935,11 +939,12 @@ def main():
     if not args.only_spmv and args.cg_solves > 0:
         log("[bench] CG solves")
         cg = cg_leg(A, p, torch, dev, args.cg_solves)
+        cg["jacobi"] = cg_leg(A, p, torch, dev, max(3, args.cg_solves // 4), mode="jacobi")
         xo = ref_solution(f"hpcg27_{args.n}")
-        if xo is not None:
-            cg["err_vs_oracle_fp64"] = float(np.linalg.norm(cg.pop("_x") - xo) / np.linalg.norm(xo))
-        else:
-            cg.pop("_x", None)
+        for r in (cg, cg["jacobi"]):
+            xs = r.pop("_x")
+            if xo is not None:
+                r["err_vs_oracle_fp64"] = float(np.linalg.norm(xs - xo) / np.linalg.norm(xo))
 
     go = not args.only_spmv
     small = small_bench(dsm, ctx, torch, dev) if go and not args.no_small else None

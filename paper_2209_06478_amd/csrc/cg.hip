@@ -552,11 +552,11 @@ __global__ void __launch_bounds__(CGB) k_pcg_init(i64 n, const double *b, const 
     }
 }
 
-__global__ void __launch_bounds__(CGB) k_pcg_init_state(const double *part_rz, const double *part_rr, CgState *st,
-                                                        double tol, long long maxit) {
+__global__ void __launch_bounds__(CGB) k_pcg_init_state(const double *part_rz, const double *part_rr, int count,
+                                                        CgState *st, double tol, long long maxit) {
     __shared__ double lds[CGB / WAVE];
-    const double rz = reduce_partials(part_rz, lds);
-    const double rr = reduce_partials(part_rr, lds);
+    const double rz = reduce_partials(part_rz, lds, count);
+    const double rr = reduce_partials(part_rr, lds, count);
     if (threadIdx.x == 0) {
         st->rho[0] = rz;
         st->rho[1] = 0;
@@ -571,11 +571,11 @@ __global__ void __launch_bounds__(CGB) k_pcg_init_state(const double *part_rz, c
 }
 
 __global__ void __launch_bounds__(CGB) k_pcg_update_xr(i64 n, double *x, double *r, const double *p, const double *q,
-                                                       const double *dinv, const double *part_pq, double *part_rz,
-                                                       double *part_rr, CgState *st) {
+                                                       const double *dinv, const double *part_pq, int npq,
+                                                       double *part_rz, double *part_rr, CgState *st) {
     __shared__ double lds[CGB / WAVE];
     if (wg_done(&st->done)) return;
-    const double pq = reduce_partials(part_pq, lds);
+    const double pq = reduce_partials(part_pq, lds, npq);
     const long long k = st->iters;
     const double rho = st->rho[(k - 1) & 1];
     if (!(pq > 0) || !isfinite(pq)) {
@@ -604,11 +604,12 @@ __global__ void __launch_bounds__(CGB) k_pcg_update_xr(i64 n, double *x, double 
 }
 
 __global__ void __launch_bounds__(CGB) k_pcg_update_p(i64 n, const double *r, double *p, const double *dinv,
-                                                      const double *part_rz, const double *part_rr, CgState *st) {
+                                                      const double *part_rz, const double *part_rr, int count,
+                                                      CgState *st) {
     __shared__ double lds[CGB / WAVE];
     if (wg_done(&st->done)) return;
-    const double rho1 = reduce_partials(part_rz, lds);
-    const double nr = sqrt(reduce_partials(part_rr, lds));
+    const double rho1 = reduce_partials(part_rz, lds, count);
+    const double nr = sqrt(reduce_partials(part_rr, lds, count));
     const long long k = st->iters;
     const double rho = st->rho[(k - 1) & 1];
     int done = 0;
@@ -814,8 +815,11 @@ static double true_relres(dsm_matrix m, const double *b, const double *x, CgBuff
     return h[1] > 0 ? h[0] / h[1] : h[0];
 }
 
+// Jacobi-preconditioned CG (z = D^-1 r formed on the fly), with the plain
+// loop's execution: the SpMV writes the p.q partials where its format can,
+// and the iterations are replayed in chunks from a captured graph.
 static CgState run_pcg(dsm_matrix m, const double *b, double *x, CgBuffers &B, double tol, long long maxit,
-                       int every, hipStream_t s, Workspace &spws) {
+                       int every, hipStream_t s, Workspace &spws, Workspace &cgws, bool use_graph) {
     const i64 n = m->nrows;
     diagonal_op(m, B.dinv, 0, s);
     int *zero = (int *)B.norms;
@@ -825,27 +829,36 @@ static CgState run_pcg(dsm_matrix m, const double *b, double *x, CgBuffers &B, d
     DSM_HIP(hipMemcpyAsync(&hz, zero, sizeof(int), hipMemcpyDeviceToHost, s));
     DSM_HIP(hipStreamSynchronize(s));
     DSM_CHECK(hz == 0, DSM_E_INVALID, "Jacobi preconditioner needs a non-zero finite diagonal");
+    const unsigned G = vec_grid(n);
     spmv(m, m->P, x, B.q, DSM_F64, m->variant, s, &spws);
-    hipLaunchKernelGGL(k_pcg_init, dim3(CGG), dim3(CGB), 0, s, n, b, B.q, B.dinv, B.r, B.p, B.part_b, B.part_c);
-    hipLaunchKernelGGL(k_pcg_init_state, dim3(1), dim3(CGB), 0, s, B.part_b, B.part_c, B.st, tol, maxit);
+    hipLaunchKernelGGL(k_pcg_init, dim3(G), dim3(CGB), 0, s, n, b, B.q, B.dinv, B.r, B.p, B.part_b, B.part_c);
+    hipLaunchKernelGGL(k_pcg_init_state, dim3(1), dim3(CGB), 0, s, B.part_b, B.part_c, (int)G, B.st, tol, maxit);
     DSM_HIP(hipGetLastError());
-    CgState h{};
-    long long enq = 0;
-    for (;;) {
-        for (int j = 0; j < every && enq < maxit; j++, enq++) {
-            spmv(m, m->P, B.p, B.q, DSM_F64, m->variant, s, &spws, &B.st->done);
-            hipLaunchKernelGGL((k_cg_dot_pq<double>), dim3(CGG), dim3(CGB), 0, s, n, B.p, B.q, B.part_a, B.st);
-            hipLaunchKernelGGL(k_pcg_update_xr, dim3(CGG), dim3(CGB), 0, s, n, x, B.r, B.p, B.q, B.dinv, B.part_a,
-                               B.part_b, B.part_c, B.st);
-            hipLaunchKernelGGL(k_pcg_update_p, dim3(CGG), dim3(CGB), 0, s, n, B.r, B.p, B.dinv, B.part_b, B.part_c,
-                               B.st);
+    auto enqueue = [&](int, hipStream_t ss) {
+        int npq = spmv_dot(m, m->P, B.p, B.q, DSM_F64, m->variant, ss, B.part_a, &B.st->iters, &B.st->done);
+        if (npq == 0) {
+            spmv(m, m->P, B.p, B.q, DSM_F64, m->variant, ss, &spws, &B.st->done);
+            hipLaunchKernelGGL((k_cg_dot_pq<double>), dim3(G), dim3(CGB), 0, ss, n, B.p, B.q, B.part_a, B.st);
+            npq = (int)G;
         }
+        hipLaunchKernelGGL(k_pcg_update_xr, dim3(G), dim3(CGB), 0, ss, n, x, B.r, B.p, B.q, B.dinv, B.part_a, npq,
+                           B.part_b, B.part_c, B.st);
+        hipLaunchKernelGGL(k_pcg_update_p, dim3(G), dim3(CGB), 0, ss, n, B.r, B.p, B.dinv, B.part_b, B.part_c,
+                           (int)G, B.st);
         DSM_HIP(hipGetLastError());
-        DSM_HIP(hipMemcpyAsync(&h, B.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-        DSM_HIP(hipStreamSynchronize(s));
-        if (h.done || enq >= maxit) break;
+    };
+    std::string key;
+    if (use_graph) {
+        const Payload &P = m->P;
+        char buf[512];
+        snprintf(buf, sizeof buf, "pcgj|%p|%d|%d|%d|%lld|%lld|%lld|%lld|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%p|%lld",
+                 (void *)m, P.fmt, P.vdt, m->variant, (long long)P.ndiag, (long long)P.K, (long long)P.csr_nnz,
+                 (long long)P.coo_nnz, (void *)P.rp, (void *)P.dval, (void *)P.evl, (void *)P.cval, (void *)x,
+                 (void *)B.r, (void *)B.p, (void *)B.q, (void *)B.dinv, (void *)B.part_a, (void *)B.part_b,
+                 (void *)B.part_c, (void *)B.st, every, spws.p, (long long)n);
+        key = buf;
     }
-    return h;
+    return run_chunks(cgws, key, use_graph, every, maxit, B.st, s, enqueue);
 }
 
 static int default_check_every(i64 n) { return n < 100000 ? 32 : 8; }
@@ -872,7 +885,12 @@ void cg_solve_ws(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o,
         return;
     }
     if (o.mode == DSM_CG_JACOBI) {
-        CgState h = run_pcg(m, b, x, B, o.tol, maxit, every, s, spws);
+        // replayed on a workspace copy of x, as the plain loop below
+        const bool graphed = use_graph && cg_graphs_enabled();
+        double *xi = graphed ? B.xw : x;
+        if (graphed) DSM_HIP(hipMemcpyAsync(xi, x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
+        CgState h = run_pcg(m, b, xi, B, o.tol, maxit, every, s, spws, cgws, graphed);
+        if (graphed) DSM_HIP(hipMemcpyAsync(x, xi, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
         R.iters = h.iters;
         R.relres = h.relres;
         R.status = h.done == 1 ? DSM_OK : h.done == 3 ? DSM_E_BREAKDOWN : DSM_E_NOT_CONVERGED;

@@ -79,6 +79,27 @@ def test_jacobi_pcg_matches_oracle(fmt):
     A.close()
 
 
+@pytest.mark.parametrize("fmt", ["csr", "dia"])
+def test_jacobi_pcg_graph_matches_eager(fmt, monkeypatch):
+    """The Jacobi loop replayed from a captured graph (on a workspace copy of
+    x, reused by a second solve into a new x) gives the eager launches'
+    bits and iteration count."""
+    torch, dev = torch_dev()
+    p, val, b = scaled_spd()
+    A = dsm.Matrix.from_csr(ctx(), p.nrows, p.ncols, p.row_ptr, p.col, val)
+    A.convert(fmt)
+    bd = torch.from_numpy(b).to(dev)
+    monkeypatch.setenv("DSM_CG_GRAPH", "0")
+    xe, re = A.cg(bd, tol=1e-10, mode="jacobi")
+    xe = xe.cpu().numpy()
+    monkeypatch.setenv("DSM_CG_GRAPH", "1")
+    for rep in range(2):
+        xg, rg = A.cg(bd, x=torch.zeros(p.nrows, dtype=torch.float64, device=dev), tol=1e-10, mode="jacobi")
+        assert rg["iters"] == re["iters"] and rg["status"] == "converged", (rep, rg, re)
+        assert np.array_equal(xg.cpu().numpy().view(np.uint64), xe.view(np.uint64)), rep
+    A.close()
+
+
 def test_jacobi_pcg_hpcg_equals_plain():
     torch, dev = torch_dev()
     p = problem("hpcg16")

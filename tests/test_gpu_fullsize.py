@@ -77,6 +77,27 @@ def test_fp64_cg_hpcg104_bench_sweeps(variant):
     A.close()
 
 
+@pytest.mark.parametrize("variant", [16, "selected"])
+def test_jacobi_pcg_hpcg104(variant):
+    """Jacobi PCG on HPCG 104^3, as the benchmark runs it: the diagonal is
+    26 in every row, and with M = c I the preconditioned iterates are CG's
+    (z = r / c scales p by 1/c and alpha by c), so CG's oracle checks
+    apply."""
+    torch, dev = torch_dev()
+    p = problem("hpcg104")
+    A = make_matrix(p)
+    if variant == "selected":
+        A.select(use_cache=False)
+    else:
+        A.convert("dia")
+        A.variant = variant
+    b = torch.from_numpy(p.b).to(dev)
+    x, res = A.cg(b, tol=1e-10, mode="jacobi")
+    log(f"[fullsize] hpcg104 jacobi {A.format} v{A.variant}")
+    check_fp64_cg("hpcg104", x.cpu().numpy(), res)
+    A.close()
+
+
 @pytest.mark.parametrize("name", ["hpcg128", "aniso128"])
 @pytest.mark.parametrize("vdt", ["f32", "bf16"])
 @pytest.mark.parametrize("fmt", ["dia", "csr"])
