@@ -408,6 +408,10 @@ def irregular_bench(dsm, ctx, torch, dev):
         log(f"[bench] selection on {name}")
         p = gen()
         bounds = gather_bounds(dsm, torch, dev, p)
+        xg = torch.from_numpy(inputs.uniform_vector(p.ncols)).to(dev)
+        C = dsm.Matrix.from_csr(ctx, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
+        vendor = vendor_csr(torch, dev, p, xg, y_lib=C.spmv(xg))
+        C.close()
         for vdt in ("f64", "f32"):
             # the cost model's pick first (no profiling runs; the model has
             # only learned from the matrices timed before this one)
@@ -435,7 +439,79 @@ def irregular_bench(dsm, ctx, torch, dev):
                                     "model_choice_slowdown": round(t[mrep["chosen"]] / t[rep["chosen"]], 3)
                                     if mrep["chosen"] in t else None,
                                     "bounds_fp64_x": bounds}
+            if vdt == "f64":
+                if "us" in vendor:
+                    vendor["speedup_selected_vs_vendor"] = round(vendor["us"] / t[rep["chosen"]], 3)
+                out[f"{name}_{vdt}"]["vendor_csr"] = vendor
             A.close()
+    return out
+
+
+def vendor_csr(torch, dev, p, x, y_lib=None, reps=50):
+    """Informational comparator, not part of the library's path: the vendor
+    library's CSR SpMV (rocSPARSE's csrmv, called through its C API) on the
+    same FP64 matrix and x.  Its analysis step runs once, then `reps`
+    compute calls back to back on torch's current stream, each bracketed
+    by HIP events (median).  Returns the time, the rate over the CSR
+    algorithmic bytes and, given the library's y, the largest |difference|
+    over the row scale sum_j |a_ij x_j| (computed on the host)."""
+    import ctypes as C
+    import numpy as np
+    out = {"library": "rocSPARSE dcsrmv (analysis once, compute calls timed)"}
+    vp = C.c_void_p
+    try:
+        rs = C.CDLL("librocsparse.so.1")
+    except OSError as e:
+        out["error"] = f"librocsparse not loadable: {e}"[:300]
+        return out
+    h, descr, info = vp(), vp(), vp()
+
+    def ok(st, what):
+        if st != 0:
+            raise RuntimeError(f"rocsparse_{what} returned status {st}")
+
+    try:
+        ok(rs.rocsparse_create_handle(C.byref(h)), "create_handle")
+        ok(rs.rocsparse_set_stream(h, vp(torch.cuda.current_stream().cuda_stream)), "set_stream")
+        ok(rs.rocsparse_create_mat_descr(C.byref(descr)), "create_mat_descr")
+        ok(rs.rocsparse_create_mat_info(C.byref(info)), "create_mat_info")
+        crow = torch.from_numpy(p.row_ptr.astype(np.int32)).to(dev)
+        colt = torch.from_numpy(p.col.astype(np.int32)).to(dev)
+        val = torch.from_numpy(p.val).to(dev)
+        yv = torch.empty(p.nrows, dtype=torch.float64, device=dev)
+        none_op = C.c_int(111)  # rocsparse_operation_none
+        m, n, nnz = C.c_int32(p.nrows), C.c_int32(p.ncols), C.c_int32(p.nnz)
+        mat = (descr, vp(val.data_ptr()), vp(crow.data_ptr()), vp(colt.data_ptr()), info)
+        ok(rs.rocsparse_dcsrmv_analysis(h, none_op, m, n, nnz, *mat), "dcsrmv_analysis")
+        alpha, beta = C.c_double(1.0), C.c_double(0.0)
+        xp, yp = vp(x.data_ptr()), vp(yv.data_ptr())
+
+        def mv():
+            ok(rs.rocsparse_dcsrmv(h, none_op, m, n, nnz, C.byref(alpha), *mat, xp, C.byref(beta), yp), "dcsrmv")
+
+        for _ in range(5):
+            mv()
+        us = float(np.median(event_times_us(torch, mv, reps)))
+        nbytes = p.nnz * 12 + (p.nrows + 1) * 4 + 16 * p.nrows
+        out.update(us=round(us, 2), gbps=round(nbytes / (us * 1e-6) / 1e9, 1),
+                   gflops=round(2 * p.nnz / (us * 1e-6) / 1e9, 1))
+        if y_lib is not None:
+            xa = np.abs(x.cpu().numpy())
+            rows = np.repeat(np.arange(p.nrows), np.diff(p.row_ptr))
+            scale = np.bincount(rows, weights=np.abs(p.val) * xa[p.col], minlength=p.nrows)
+            diff = np.abs(yv.cpu().numpy() - y_lib.cpu().numpy())
+            out["max_row_scaled_diff_vs_library"] = float(np.max(diff / np.maximum(scale, 1e-300)))
+        torch.cuda.synchronize()
+        del crow, colt, val, yv
+    except Exception as e:  # informational only: record why it did not run
+        out["error"] = f"{type(e).__name__}: {e}"[:300]
+    finally:
+        if info:
+            rs.rocsparse_destroy_mat_info(info)
+        if descr:
+            rs.rocsparse_destroy_mat_descr(descr)
+        if h:
+            rs.rocsparse_destroy_handle(h)
     return out
 
 
@@ -842,6 +918,9 @@ def main():
     csr_bytes = p.nnz * 12 + (p.nrows + 1) * 4 + 16 * p.nrows
     csr_avg = float(np.mean(csr_us))
     csr_cold = cold_times(max(10, args.steps // 10))
+    log("[bench] vendor CSR SpMV (informational)")
+    spmv()
+    vendor = vendor_csr(torch, dev, p, x, y_lib=y, reps=args.steps)
 
     sel = None
     if args.format:
@@ -1000,6 +1079,11 @@ def main():
                       "gflops": round(2 * nnz / (csr_avg * 1e-6) / 1e9, 1), "bytes": int(csr_bytes),
                       "cold_avg_us": round(float(csr_cold.mean()), 3),
                       "cold_gbps": round(csr_bytes / (float(csr_cold.mean()) * 1e-6) / 1e9, 1)},
+        "vendor_csr": dict(vendor, **({"fixed_csr_median_us": round(float(np.median(csr_us)), 2),
+                                         "selected_median_us": round(float(np.median(warm)), 2),
+                                         "speedup_fixed_csr_vs_vendor": round(vendor["us"] / float(np.median(csr_us)), 3),
+                                         "speedup_selected_vs_vendor": round(vendor["us"] / float(np.median(warm)), 3)}
+                                      if "us" in vendor else {})),
         "speedup_vs_fixed_csr": round(csr_avg / warm_avg, 3),
         "speedup_vs_fixed_csr_cold": round(float(csr_cold.mean()) / cold_avg, 3),
         # against CSR with its kernel tuned too (the selection's own CSR median)
