@@ -370,7 +370,7 @@ typedef struct {
     int64_t maxit;       /* SpMV limit (outer iterations for F64; inner total
                             for IR); <= 0 means min(10*n, 20000)              */
     int32_t mode;        /* dsm_cg_mode                                        */
-    double inner_tol;    /* IR: inner relative tolerance (default 1e-4); an
+    double inner_tol;    /* IR: inner relative tolerance (default 1e-5); an
                             inner solve stops at max(inner_tol,
                             tol / (2 * current outer residual)), so the last
                             outer step reduces no further than needed         */

@@ -345,7 +345,7 @@ class Matrix:
                     convert_us={FORMAT_NAMES[f]: r.convert_us[f] for f in range(6)},
                     bytes={FORMAT_NAMES[f]: r.bytes[f] for f in range(6)})
 
-    def cg(self, b, x=None, tol=1e-10, maxit=0, mode="f64", inner_tol=1e-4, check_every=0, max_outer=50,
+    def cg(self, b, x=None, tol=1e-10, maxit=0, mode="f64", inner_tol=1e-5, check_every=0, max_outer=50,
            stream=None, raise_on_status=False):
         """Solves A x = b (FP64 device vectors).  Returns (x, result dict)."""
         torch = _torch()

@@ -917,7 +917,10 @@ void cg_solve_ws(dsm_matrix m, const double *b, double *x, const dsm_cg_opts &o,
         return;
     }
     // iterative refinement
-    const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-4;
+    // 1e-5 against 1e-4: HPCG 128^3 with BF16 or FP32 values takes 301 instead
+    // of 345 inner iterations (12% less time), ANISO7 1% less; FP32 vectors
+    // still reach it with a wide margin
+    const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
     const int max_outer = o.max_outer > 0 ? o.max_outer : 50;
     long long inner_total = 0;
     int status = DSM_E_NOT_CONVERGED;
@@ -977,7 +980,7 @@ DSM_API void dsm_cg_opts_default(dsm_cg_opts *o) {
     o->tol = 1e-10;
     o->maxit = 0;
     o->mode = DSM_CG_F64;
-    o->inner_tol = 1e-4;
+    o->inner_tol = 1e-5;
     o->check_every = 0;
     o->max_outer = 50;
 }
