@@ -221,7 +221,9 @@ def cpu_baseline_line(res, n):
 
 def ir_bench(dsm, ctx, torch, dev, n=128):
     """FP64 plain CG vs iterative refinement with FP32/BF16 values on HPCG n^3
-    and ANISO7 n^3 (z-coupling x100), all to 1e-10 relative residual."""
+    and ANISO7 n^3 (z-coupling x100), all to 1e-10 relative residual; IR
+    with the inner Krylov space restarted at every refinement step, and with
+    the search direction continued across steps."""
     import numpy as np
     import inputs
     out = {}
@@ -231,11 +233,13 @@ def ir_bench(dsm, ctx, torch, dev, n=128):
         b = torch.from_numpy(p.b).to(dev)
         row = {}
         for label, fmt, vdt, mode in (("f64_csr", "csr", "f64", "f64"), ("f64_dia", "dia", "f64", "f64"),
-                                      ("ir_f32_dia", "dia", "f32", "ir"), ("ir_bf16_dia", "dia", "bf16", "ir")):
+                                      ("ir_f32_dia", "dia", "f32", "ir"), ("ir_bf16_dia", "dia", "bf16", "ir"),
+                                      ("ir_cont_f32_dia", "dia", "f32", "ir_cont"),
+                                      ("ir_cont_bf16_dia", "dia", "bf16", "ir_cont")):
             A = dsm.Matrix.from_csr(ctx, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
             # the format is fixed; the kernel variant is tuned for the vector
             # type the loop's SpMV runs in (FP32 inside IR)
-            A.select(mask=[fmt], value_dtype=vdt, vec_dtype="f32" if mode == "ir" else "f64", use_cache=False)
+            A.select(mask=[fmt], value_dtype=vdt, vec_dtype="f32" if mode != "f64" else "f64", use_cache=False)
             ts, res, x = [], None, None
             for rep in range(3):
                 x0 = torch.zeros(p.nrows, dtype=torch.float64, device=dev)

@@ -360,9 +360,18 @@ typedef enum {
                          update; inner CG in FP32 vectors with FP32 SpMV
                          accumulation and FP64 dot accumulation (values must
                          be F32 or BF16)                                      */
-    DSM_CG_JACOBI = 2 /* FP64 CG preconditioned with M = diag(A) (the diagonal
-                         from dsm_extract_diagonal; a zero diagonal entry gives
-                         DSM_E_INVALID); stops on ||r|| <= tol ||r0||          */
+    DSM_CG_JACOBI = 2, /* FP64 CG preconditioned with M = diag(A) (the
+                         diagonal from dsm_extract_diagonal; a zero diagonal
+                         entry gives DSM_E_INVALID); stops on
+                         ||r|| <= tol ||r0||                                   */
+    DSM_CG_IR_CONT = 3 /* iterative refinement as DSM_CG_IR, but every inner
+                         solve after the first continues the previous one's
+                         search direction: its first direction is the new
+                         scaled residual plus the last inner direction times
+                         the CG step coefficient, as if the previous inner CG
+                         had gone on with its recursive residual replaced by
+                         the FP64 one (a reliable update), so the Krylov
+                         space is not restarted at every outer step        */
 } dsm_cg_mode;
 
 typedef struct {
@@ -370,7 +379,9 @@ typedef struct {
     int64_t maxit;       /* SpMV limit (outer iterations for F64; inner total
                             for IR); <= 0 means min(10*n, 20000)              */
     int32_t mode;        /* dsm_cg_mode                                        */
-    double inner_tol;    /* IR: inner relative tolerance (default 1e-5); an
+    double inner_tol;    /* IR: inner relative tolerance; <= 0 (the default)
+                            takes the mode's: 1e-5 for DSM_CG_IR, 1e-2 for
+                            DSM_CG_IR_CONT; an
                             inner solve stops at max(inner_tol,
                             tol / (2 * current outer residual)), so the last
                             outer step reduces no further than needed         */

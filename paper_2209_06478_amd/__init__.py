@@ -18,7 +18,7 @@ import numpy as np
 
 from . import _lib as L
 from ._lib import (COO, CSR, DIA, ELL, HYB, HDC, F64, F32, BF16, FORMATS, FORMAT_NAMES, DTYPES, DTYPE_NAMES,
-                   CG_F64, CG_IR, CG_JACOBI, PROBE_PARTIALS)
+                   CG_F64, CG_IR, CG_JACOBI, CG_IR_CONT, PROBE_PARTIALS)
 
 __all__ = ["Context", "Matrix", "Server", "DsmError", "lib", "COO", "CSR", "DIA", "ELL", "HYB", "HDC",
            "F64", "F32", "BF16", "FORMATS", "DTYPES", "cg_batched", "stream_probe", "gather_probe", "Multigrid"]
@@ -345,7 +345,7 @@ class Matrix:
                     convert_us={FORMAT_NAMES[f]: r.convert_us[f] for f in range(6)},
                     bytes={FORMAT_NAMES[f]: r.bytes[f] for f in range(6)})
 
-    def cg(self, b, x=None, tol=1e-10, maxit=0, mode="f64", inner_tol=1e-5, check_every=0, max_outer=50,
+    def cg(self, b, x=None, tol=1e-10, maxit=0, mode="f64", inner_tol=0, check_every=0, max_outer=50,
            stream=None, raise_on_status=False):
         """Solves A x = b (FP64 device vectors).  Returns (x, result dict)."""
         torch = _torch()
@@ -368,7 +368,7 @@ def _cg_opts(tol, maxit, mode, inner_tol, check_every, max_outer):
     o = L.CgOpts()
     lib().dsm_cg_opts_default(C.byref(o))
     o.tol, o.maxit = tol, int(maxit)
-    o.mode = {"f64": CG_F64, "ir": CG_IR, "jacobi": CG_JACOBI}[mode] if isinstance(mode, str) else int(mode)
+    o.mode = {"f64": CG_F64, "ir": CG_IR, "jacobi": CG_JACOBI, "ir_cont": CG_IR_CONT}[mode] if isinstance(mode, str) else int(mode)
     o.inner_tol, o.check_every, o.max_outer = inner_tol, int(check_every), int(max_outer)
     return o
 

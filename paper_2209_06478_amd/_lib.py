@@ -11,7 +11,7 @@ FORMAT_NAMES = {v: k for k, v in FORMATS.items()}
 F64, F32, BF16 = 0, 1, 2
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
 DTYPE_NAMES = {v: k for k, v in DTYPES.items()}
-CG_F64, CG_IR, CG_JACOBI = 0, 1, 2
+CG_F64, CG_IR, CG_JACOBI, CG_IR_CONT = 0, 1, 2, 3
 
 OK = 0
 E_INVALID, E_NOMEM, E_INFEASIBLE, E_UNSUPPORTED = -1, -2, -3, -4

@@ -284,7 +284,7 @@ DSM_API dsm_status dsm_server_submit(dsm_server s, dsm_matrix m, const double *b
         it.small = o.mode == DSM_CG_F64 && batch_eligible(m, s->opts.small_rows);
         it.matrix = m->P.bytes;
         it.ws[WS_BATCH] = it.small ? batch_request_bytes(m->nrows) : 0;
-        it.ws[WS_CG] = it.small ? 0 : cg_workspace_bytes(m->nrows, o.mode == DSM_CG_IR);
+        it.ws[WS_CG] = it.small ? 0 : cg_workspace_bytes(m->nrows, o.mode == DSM_CG_IR || o.mode == DSM_CG_IR_CONT);
         it.ws[WS_SPMV] = it.small ? 0 : spmv_scratch_bytes(m, m->P, DSM_F64);
         std::lock_guard<std::mutex> lk(s->mu);
         s->refresh();

@@ -98,10 +98,11 @@ def test_jacobi_pcg_hpcg104(variant):
     A.close()
 
 
+@pytest.mark.parametrize("mode", ["ir", "ir_cont"])
 @pytest.mark.parametrize("name", ["hpcg128", "aniso128"])
 @pytest.mark.parametrize("vdt", ["f32", "bf16"])
 @pytest.mark.parametrize("fmt", ["dia", "csr"])
-def test_ir_128(name, vdt, fmt):
+def test_ir_128(name, vdt, fmt, mode):
     """Iterative refinement with FP32/BF16 values at 128^3, the variant tuned
     for FP32 vectors as the benchmark does.  The values (26/-1, 204/-1/-100)
     are exact in both storage types, so IR solves A x = b itself: the true
@@ -115,14 +116,14 @@ def test_ir_128(name, vdt, fmt):
     A = make_matrix(p)
     rep = A.select(mask=[fmt], value_dtype=vdt, vec_dtype="f32", use_cache=False)
     b = torch.from_numpy(p.b).to(dev)
-    x, res = A.cg(b, tol=1e-10, mode="ir")
+    x, res = A.cg(b, tol=1e-10, mode=mode)
     xh = x.cpu().numpy()
     tr = oracle.true_relres(p.row_ptr, p.col, p.val, p.b, xh)
     tr64 = oracle.true_relres(p.row_ptr, p.col, p.val, p.b, x64)
     fwd = np.linalg.norm(xh - x64) / np.linalg.norm(x64)
     xnorm = np.sqrt(p.nrows)
     bound = KAPPA[name] * (tr + tr64) * xnorm / np.linalg.norm(x64)
-    log(f"[fullsize-ir] {name} {fmt} {vdt} v{rep['chosen_variant']}: outer {res['outer_iters']} inner "
+    log(f"[fullsize-ir] {name} {fmt} {vdt} {mode} v{rep['chosen_variant']}: outer {res['outer_iters']} inner "
         f"{res['iters']} (fp64 CG {it64}), true relres {tr:.2e}, ||x_IR - x_64||/||x_64|| {fwd:.2e} "
         f"(bound {bound:.2e}), ||x_IR - 1||/||1|| {np.linalg.norm(xh - 1) / xnorm:.2e}")
     assert res["status"] == "converged", res
