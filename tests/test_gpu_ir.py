@@ -108,3 +108,23 @@ def test_ir_needs_low_precision_values():
         A.cg(torch.from_numpy(p.b).to(dev), mode="ir", raise_on_status=True)
     assert e.value.status == dsm.L.E_UNSUPPORTED
     A.close()
+
+
+@pytest.mark.parametrize("mode", ["ir", "ir_cont"])
+def test_ir_special_cases(mode):
+    """b = 0 gives x = 0 with no inner iteration; an inner-iteration limit
+    ends the solve as not converged within that many SpMVs; a NaN in b is a
+    breakdown, not a result."""
+    torch, dev = torch_dev()
+    p = problem("hpcg16")
+    A = make_matrix(p)
+    A.convert("dia", value_dtype="bf16")
+    x, res = A.cg(torch.zeros(p.nrows, dtype=torch.float64, device=dev), tol=1e-10, mode=mode)
+    assert res["status"] == "converged" and res["iters"] == 0 and not x.any()
+    x, res = A.cg(torch.from_numpy(p.b).to(dev), tol=1e-10, mode=mode, maxit=5)
+    assert res["status"] == "not_converged" and res["iters"] <= 5, res
+    bb = p.b.copy()
+    bb[11] = np.nan
+    x, res = A.cg(torch.from_numpy(bb).to(dev), tol=1e-10, mode=mode)
+    assert res["status"] == "breakdown", res
+    A.close()
