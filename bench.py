@@ -59,7 +59,7 @@ def alg_bytes(info, N, nnz, v=8, X=8):
     }[info["format_name"]]
 
 
-def cg_leg(A, p, torch, dev, solves, mode="f64"):
+def cg_leg(A, p, torch, dev, solves, mode="f64", v=8):
     """CG to 1e-10 on the matrix in its current format: solves/s, p50/p99
     latency and time per iteration (the first solve, which captures the
     iteration graph, is not counted).  mode "jacobi": CG preconditioned
@@ -83,7 +83,7 @@ def cg_leg(A, p, torch, dev, solves, mode="f64"):
     # 16 N more for a separate p.q kernel (formats whose SpMV does not write
     # the p.q partials)
     vec = (96 if mode == "jacobi" else 80) * N + (0 if info["format_name"] in ("dia", "ell") else 16 * N)
-    it_bytes = alg_bytes(info, N, p.nnz) + vec
+    it_bytes = alg_bytes(info, N, p.nnz, v=v) + vec
     return {"mode": mode, "format": info["format_name"], "variant": A.variant, "tol": 1e-10, "iters": res["iters"],
             "bytes_per_iter": int(it_bytes),
             "effective_gbps": round(it_bytes / (float(lat.mean()) * 1e-3 / max(res["iters"], 1)) / 1e9, 1),
@@ -93,6 +93,29 @@ def cg_leg(A, p, torch, dev, solves, mode="f64"):
             "ms_per_iter": round(float(lat.mean()) / max(res["iters"], 1), 4),
             "us_per_iter": round(float(lat.mean()) * 1e3 / max(res["iters"], 1), 2),
             "_x": xs.cpu().numpy()}
+
+
+def cg_legs(dsm, ctx, A, p, torch, dev, solves):
+    """CG on the selected format, Jacobi PCG, and, where storing the values in
+    BF16 loses nothing (the HPCG values 26 and -1: dsm_values_exact), the
+    same FP64 CG over BF16-stored values of the same format (its kernel
+    variant tuned for them): the same products, a quarter of the value
+    bytes.  Solutions stay in "_x"."""
+    import numpy as np
+    cg = cg_leg(A, p, torch, dev, solves)
+    cg["jacobi"] = cg_leg(A, p, torch, dev, max(3, solves // 4), mode="jacobi")
+    if A.values_exact("bf16"):
+        log("[bench] CG with the values stored in BF16 (every value exact)")
+        fmt = A.info()["format_name"]
+        B = dsm.Matrix.from_csr(ctx, p.nrows, p.ncols, p.row_ptr, p.col, p.val)
+        B.select(mask=[fmt], value_dtype="bf16", use_cache=False)
+        lb = cg_leg(B, p, torch, dev, solves, v=2)
+        lb["value_dtype"] = "bf16 (every value exact)"
+        lb["max_abs_diff_vs_f64_storage"] = float(np.max(np.abs(lb["_x"] - cg["_x"])))
+        lb["speedup_vs_f64_storage"] = round(lb["solves_per_s"] / cg["solves_per_s"], 3)
+        cg["lossless_bf16"] = lb
+        B.close()
+    return cg
 
 
 def stream_ceilings(dsm, torch, dev, mib=2048, reps=10):
@@ -852,8 +875,7 @@ def main():
         A.spmv(x, out=y)
 
     if args.leg:
-        legs = {"cg": lambda: dict(cg_leg(A, p, torch, dev, args.cg_solves),
-                                   jacobi=cg_leg(A, p, torch, dev, max(3, args.cg_solves // 4), mode="jacobi")),
+        legs = {"cg": lambda: cg_legs(dsm, ctx, A, p, torch, dev, args.cg_solves),
                 "pcg_mg": lambda: mg_bench(dsm, ctx, torch, dev, n=args.n),
                 "ir_cg": lambda: ir_bench(dsm, ctx, torch, dev),
                 "split": lambda: split_bench(dsm, ctx, torch, dev, n=args.n),
@@ -1021,10 +1043,11 @@ def main():
     cg = None
     if not args.only_spmv and args.cg_solves > 0:
         log("[bench] CG solves")
-        cg = cg_leg(A, p, torch, dev, args.cg_solves)
-        cg["jacobi"] = cg_leg(A, p, torch, dev, max(3, args.cg_solves // 4), mode="jacobi")
+        cg = cg_legs(dsm, ctx, A, p, torch, dev, args.cg_solves)
         xo = ref_solution(f"hpcg27_{args.n}")
-        for r in (cg, cg["jacobi"]):
+        for r in (cg, cg["jacobi"], cg.get("lossless_bf16")):
+            if r is None:
+                continue
             xs = r.pop("_x")
             if xo is not None:
                 r["err_vs_oracle_fp64"] = float(np.linalg.norm(xs - xo) / np.linalg.norm(xo))

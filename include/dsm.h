@@ -198,6 +198,16 @@ dsm_status dsm_export(dsm_matrix m, const dsm_export_bufs *bufs, void *stream);
  * out[5 + b] for b in 0..32 = number of rows with length in [2^(b-1), 2^b)
  * (bin 0 = empty rows).  `out` is a host array of 38 int64.  Blocking. */
 dsm_status dsm_row_stats(dsm_matrix m, int64_t *out, void *stream);
+/* Whether storing the values in `to` loses nothing (Sec. III-A: a container
+ * is parameterised by the type of the values it holds).  *exact = 1 when
+ * every stored value of the active format, cast to `to` as dsm_convert
+ * casts (round to nearest even, BF16 through FP32) and widened back, is
+ * bit for bit the same; a wider or equal `to` is always exact.  Then an SpMV
+ * that accumulates in FP64 over the narrowed values computes the same
+ * products as over the original ones, with fewer value bytes (the HPCG
+ * matrix: 26 and -1 are exact in BF16).  Runs on `stream` and blocks until
+ * the answer is known; allocates one int of scratch. */
+dsm_status dsm_values_exact(dsm_matrix m, dsm_dtype to, int32_t *exact, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* Diagonal extraction and update (Section III-D lists both; HPCG's    */

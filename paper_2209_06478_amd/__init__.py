@@ -245,6 +245,14 @@ class Matrix:
         v = list(a)
         return dict(max=v[0], min=v[1], sum=v[2], sumsq=v[3], empty=v[4], hist=np.array(v[5:], np.int64))
 
+    def values_exact(self, value_dtype, stream=None):
+        """True when converting the stored values to `value_dtype` ("f64",
+        "f32", "bf16") loses nothing (every value survives the cast bit for
+        bit)."""
+        e = C.c_int32(0)
+        _check(lib().dsm_values_exact(self.h, _dt(value_dtype), C.byref(e), _stream(stream)), "dsm_values_exact")
+        return bool(e.value)
+
     def diagonal(self, out=None, stream=None):
         """A's diagonal as an FP64 CUDA tensor of length min(nrows, ncols)."""
         torch = _torch()

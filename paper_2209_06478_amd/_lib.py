@@ -94,6 +94,7 @@ SIGNATURES = {
     "dsm_get_info": (_st, [_p, C.POINTER(Info)]),
     "dsm_export": (_st, [_p, C.POINTER(ExportBufs), _p]),
     "dsm_row_stats": (_st, [_p, C.POINTER(C.c_int64), _p]),
+    "dsm_values_exact": (_st, [_p, C.c_int32, C.POINTER(C.c_int32), _p]),
     "dsm_extract_diagonal": (_st, [_p, _p, _p]),
     "dsm_update_diagonal": (_st, [_p, _p, _p]),
     "dsm_spmv": (_st, [_p, _p, _p, C.c_int, _p]),

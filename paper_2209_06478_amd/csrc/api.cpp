@@ -416,6 +416,16 @@ DSM_API dsm_status dsm_row_stats(dsm_matrix m, int64_t *out, void *stream) {
     });
 }
 
+DSM_API dsm_status dsm_values_exact(dsm_matrix m, dsm_dtype to, int32_t *exact, void *stream) {
+    return guard([&] {
+        check_matrix(m);
+        DSM_CHECK(exact, DSM_E_INVALID, "exact is null");
+        DSM_CHECK(to == DSM_F64 || to == DSM_F32 || to == DSM_BF16, DSM_E_INVALID, "unknown value dtype");
+        set_device(m->ctx);
+        *exact = values_exact(m, to, (hipStream_t)stream) ? 1 : 0;
+    });
+}
+
 DSM_API dsm_status dsm_spmv(dsm_matrix m, const void *x, void *y, dsm_dtype vec_dtype, void *stream) {
     return guard([&] {
         check_matrix(m);

@@ -257,6 +257,29 @@ __global__ void k_cast(i64 n, const Wi *in, Wo *out) {
     out[i] = o;
 }
 
+// Flags a value whose cast to DTO (the cast k_cast applies), widened back,
+// differs from it bit for bit (NaN payloads and the sign of zero included).
+template <class Wi, int DTI, int DTO>
+__global__ void k_values_exact(i64 n, const Wi *in, int *bad) {
+    i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Wi w = in[i];
+    double d;
+    if constexpr (DTI == DSM_F64) {
+        memcpy(&d, &w, 8);
+    } else {
+        float f;
+        memcpy(&f, &w, 4);
+        d = (double)f;
+    }
+    const float f = (float)d;
+    const double back = DTO == DSM_F32 ? (double)f : (double)bf16_to_float(float_to_bf16(f));
+    u64 a, b;
+    memcpy(&a, &d, 8);
+    memcpy(&b, &back, 8);
+    if (a != b) *bad = 1;
+}
+
 // Dispatch helpers over the value storage width.
 #define DSM_BY_DTYPE(dt, ...)                                                            \
     switch (dt) {                                                                        \
@@ -1078,6 +1101,38 @@ Payload coo_to_csr_payload(dsm_matrix m, const i32 *row, const i32 *col, const d
 }
 
 // ---------------------------------------------------------------- stats
+bool values_exact(dsm_matrix m, int to, hipStream_t s) {
+    const Payload &P = m->P;
+    // widening (or keeping) the value type is exact; narrowing order F64, F32, BF16
+    if (to <= P.vdt) return true;
+    Tmp flag(m->ctx, sizeof(int));
+    DSM_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
+    auto check = [&](const void *v, i64 n) {
+        if (!v || n <= 0) return;
+        dim3 g(grid_for(n, CB)), b(CB);
+        if (P.vdt == DSM_F64 && to == DSM_F32)
+            hipLaunchKernelGGL((k_values_exact<u64, DSM_F64, DSM_F32>), g, b, 0, s, n, (const u64 *)v, flag.as<int>());
+        else if (P.vdt == DSM_F64)
+            hipLaunchKernelGGL((k_values_exact<u64, DSM_F64, DSM_BF16>), g, b, 0, s, n, (const u64 *)v, flag.as<int>());
+        else
+            hipLaunchKernelGGL((k_values_exact<u32, DSM_F32, DSM_BF16>), g, b, 0, s, n, (const u32 *)v, flag.as<int>());
+        DSM_HIP(hipGetLastError());
+    };
+    // every stored value of the active format (padding slots hold +0, exact)
+    switch (P.fmt) {
+    case DSM_CSR: check(P.val, P.csr_nnz); break;
+    case DSM_COO: check(P.cval, P.coo_nnz); break;
+    case DSM_DIA: check(P.dval, P.ndiag * P.pitch); break;
+    case DSM_ELL: check(P.evl, P.K * P.pitch); break;
+    case DSM_HYB: check(P.evl, P.K * P.pitch); check(P.cval, P.coo_nnz); break;
+    case DSM_HDC: check(P.dval, P.ndiag * P.pitch); check(P.val, P.csr_nnz); break;
+    }
+    int h = 0;
+    DSM_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    DSM_HIP(hipStreamSynchronize(s));
+    return h == 0;
+}
+
 void row_stats(dsm_matrix m, i64 *out, hipStream_t s) {
     dsm_ctx ctx = m->ctx;
     const i64 n = m->nrows;

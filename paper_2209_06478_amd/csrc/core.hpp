@@ -156,6 +156,9 @@ Payload cast_csr(dsm_matrix m, const Payload &csr, int vdt, hipStream_t s);
 Payload coo_to_csr_payload(dsm_matrix m, const i32 *row, const i32 *col, const double *val,
                            i64 nnz, bool sorted, hipStream_t s);
 void row_stats(dsm_matrix m, i64 *out, hipStream_t s);
+// Whether every stored value of the active format casts to `to` and back
+// unchanged (blocking)
+bool values_exact(dsm_matrix m, int to, hipStream_t s);
 // Structure of a CSR payload that decides every format's size, computed
 // on the device without building the formats: longest row, HYB width and
 // overflow, number of diagonals, HDC's well-filled diagonals and the entries

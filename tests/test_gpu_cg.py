@@ -233,3 +233,36 @@ def test_cg_fused_maxit_and_breakdown(fused):
     finally:
         os.environ.pop("DSM_CG_FUSED", None)
     A.close()
+
+
+def test_values_exact_and_lossless_narrow_storage():
+    """dsm_values_exact: the HPCG values (26, -1) survive a cast to FP32 and
+    BF16, N(0,1) values do not; from FP32 storage BF16 is checked on the FP32
+    words; widening is always exact.  FP64 CG over DIA values stored in BF16
+    (exact) gives the iterates of FP64 storage bit for bit when the same
+    sweep runs, and the oracle's iteration count."""
+    torch, dev = torch_dev()
+    p = problem("hpcg16")
+    A = make_matrix(p)
+    assert A.values_exact("f32") and A.values_exact("bf16") and A.values_exact("f64")
+    q = inputs.banded_spd(2000, 8, seed=21)
+    Q = make_matrix(q)
+    assert not Q.values_exact("f32") and not Q.values_exact("bf16") and Q.values_exact("f64")
+    for fmt in ("csr", "dia", "ell", "hyb", "hdc", "coo"):
+        Q.convert(fmt)
+        assert not Q.values_exact("bf16"), fmt
+    Q.convert("csr", value_dtype="f32")
+    assert Q.values_exact("f32") and Q.values_exact("f64") and not Q.values_exact("bf16")
+    Q.close()
+    b = torch.from_numpy(p.b).to(dev)
+    _, it, _, _ = oracle.cg(p.row_ptr, p.col, p.val, p.b, tol=1e-10)
+    sols = []
+    for vdt in ("f64", "bf16"):
+        A.convert("dia", value_dtype=vdt)
+        A.variant = 0
+        x, res = A.cg(b, tol=1e-10)
+        assert res["status"] == "converged" and abs(res["iters"] - it) <= 1, (vdt, res, it)
+        sols.append((x.cpu().numpy(), res["iters"]))
+    assert sols[0][1] == sols[1][1]
+    assert np.array_equal(sols[0][0], sols[1][0])
+    A.close()
