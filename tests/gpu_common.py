@@ -148,6 +148,19 @@ def selection_retime(p, A, rep, value_dtype="f64", rounds=3, warmup=3, reps=20):
     return chosen, med[best], f"{best[0]} v{best[1]}"
 
 
+def selection_acceptable(rep, chosen_t, best_t, best_label, slack=1.05, tie=1.02):
+    """Acceptance of a selection against the re-timing: the chosen median
+    within 5% of the best one.  A choice that won the selection's tie rule
+    (within 2%, fewer algorithmic bytes) may sit up to 2% behind the best
+    at selection time, so when the re-timed best has more bytes than the
+    choice the bound widens by that window."""
+    best_fmt = best_label.split()[0]
+    if chosen_t <= slack * best_t:
+        return True
+    fewer_bytes = rep["bytes"][rep["chosen"]] < rep["bytes"].get(best_fmt, 0)
+    return fewer_bytes and chosen_t <= slack * tie * best_t
+
+
 def selection_retime_cold(p, A, rep, rounds=3, reps=15, flush_mib=1024):
     """As selection_retime, with the cold protocol of a selection run with
     flush_bytes: every timed SpMV starts after a read of a 1 GiB buffer and

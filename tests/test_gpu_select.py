@@ -8,7 +8,7 @@ import pytest
 import inputs
 import oracle
 import paper_2209_06478_amd as dsm
-from gpu_common import selection_retime_cold, log, make_matrix, median_launch_us, problem, row_scaled_err, selection_retime, torch_dev, x_for
+from gpu_common import selection_acceptable, selection_retime_cold, log, make_matrix, median_launch_us, problem, row_scaled_err, selection_retime, torch_dev, x_for
 
 pytestmark = pytest.mark.gpu
 
@@ -29,7 +29,7 @@ def test_select_is_near_best(name):
     assert row_scaled_err(A.spmv(x).cpu().numpy(), yref, scale) <= 1e-14
     chosen_t, best_t, best_f = selection_retime(p, A, rep)
     log(f"[select] {name}: chosen {chosen_t:.2f} us, best re-timed {best_f} {best_t:.2f} us")
-    assert chosen_t <= 1.05 * best_t
+    assert selection_acceptable(rep, chosen_t, best_t, best_f), (rep["bytes"], chosen_t, best_t, best_f)
     A.close()
 
 
@@ -50,7 +50,7 @@ def test_cold_select_is_near_best(name):
     assert row_scaled_err(A.spmv(x).cpu().numpy(), yref, scale) <= 1e-14
     chosen_t, best_t, best_f = selection_retime_cold(p, A, rep)
     log(f"[select cold] {name}: chosen {chosen_t:.2f} us, best re-timed {best_f} {best_t:.2f} us")
-    assert chosen_t <= 1.05 * best_t
+    assert selection_acceptable(rep, chosen_t, best_t, best_f), (rep["bytes"], chosen_t, best_t, best_f)
     A.close()
 
 
