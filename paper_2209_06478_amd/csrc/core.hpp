@@ -227,8 +227,10 @@ double spmv_kernel_us(dsm_matrix m, const void *x, void *y, int vdt, hipStream_t
 // writing DSM_PROBE_PARTIALS partial sums to part: evicts L2 and the
 // Infinity Cache of what was there when bytes exceed their capacity.
 void flush_read(const void *buf, i64 bytes, double *part, hipStream_t s);
-constexpr int DIA_CLUSTER_K = 3;
-constexpr int DIA_CLUSTER_SPAN = 64;
+// diagonal clusters of the LDS-staged DIA sweep: at most 9 diagonals whose
+// offsets lie within 256 of the first (one z-plane of a 27-point stencil)
+constexpr int DIA_CLUSTER_K = 9;
+constexpr int DIA_CLUSTER_SPAN = 256;
 
 // ---------------------------------------------------------------- cg.hip / batched.hip
 // CG with caller-provided workspaces (vectors/scalars, SpMV scratch).

@@ -418,12 +418,12 @@ __global__ void __launch_bounds__(SB) k_dia(i64 nrows, i64 ncols, i64 ndiag, con
 }
 
 // One cluster of the LDS-staged sweep (the records clusters.hpp builds).
-struct alignas(32) CluRec {
+struct alignas(64) CluRec {
     i32 kb, ke, lo, hi;
-    i32 d[4];  // offsets of diagonals kb.. relative to lo, 0 past ke
+    i32 d[CLU_MAXK];  // offsets of diagonals kb.. relative to lo, 0 past ke
 };
 static_assert(sizeof(CluRec) == CLU_REC * sizeof(i32), "cluster record layout");
-static_assert(DIA_CLUSTER_K <= 4, "a cluster record holds four relative offsets");
+static_assert(DIA_CLUSTER_K <= CLU_MAXK, "a cluster record holds CLU_MAXK relative offsets");
 
 // DIA sweep with x staged in LDS (variant bit 4).  A workgroup owns
 // T = SB*R*RW consecutive rows (thread t: rows r0 + t*RW + q*SB*RW (+1 with
@@ -431,7 +431,7 @@ static_assert(DIA_CLUSTER_K <= 4, "a cluster record holds four relative offsets"
 // nearby diagonals (offsets lo..hi, at most DIA_CLUSTER_SPAN apart) it
 // loads the x window [r0 + lo, r0 + hi + T) once, coalesced, into LDS, and
 // every diagonal of the cluster reads its operands there instead of
-// gathering them from L2: the 27 diagonals of a 27-point stencil need 9
+// gathering them from L2: the 27 diagonals of a 27-point stencil need 3
 // window loads instead of 27 gathers.  Columns outside the matrix read +0
 // (their slots are padding, +0); zero slots drop their operand as in k_dia.
 // Measured faster than k_dia beyond the Infinity Cache (HPCG 128^3 and
@@ -447,12 +447,14 @@ __global__ void __launch_bounds__(SB) k_dia_lds(i64 nrows, i64 ncols, i64 nclu, 
     constexpr int T = SB * R * RW;
     constexpr int WMAX = T + DIA_CLUSTER_SPAN;
     constexpr int WP = (WMAX + SB - 1) / SB;
+    // A cluster holds up to KC = 9 diagonals (the nine of one z-plane of a
+    // 27-point stencil), so one cluster's value loads keep 9 (18 with row
+    // pairs) loads per thread in flight, and a 27-point sweep has three
+    // windows and six barriers.  Clusters of at most 3 diagonals (64 apart)
+    // needed the loads of three clusters issued together to reach the same
+    // depth and nine windows and eighteen barriers: 46.8 against 45.0-45.4
+    // us for the cold sweep of HPCG 104^3 (variant 56) on one box.
     constexpr int KC = DIA_CLUSTER_K;
-    // The cold-streaming form (nontemporal value loads) issues the loads of
-    // PG clusters at once, so a workgroup keeps more HBM requests in flight
-    // through the barriers and products of the first ones.
-    constexpr bool PF = NT;
-    constexpr int PG = 3;
     __shared__ X xs[WMAX];
     const u32 b = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
     const i64 r0 = (i64)b * T;
@@ -550,26 +552,10 @@ __global__ void __launch_bounds__(SB) k_dia_lds(i64 nrows, i64 ncols, i64 nclu, 
                     s[q][w] += wv * (wv != (X)0 ? xv : (X)0);
                 }
     };
-    if constexpr (PF) {
-        // groups of PG clusters: every load of a group is issued before the
-        // first of its clusters is consumed (loads carried over a loop
-        // iteration would be waited for at its start).  The loads are unconditional - a stage past the last
-        // cluster reloads the last one and is not consumed - so the compiler
-        // can count exactly how many are in flight behind each stage.
-        for (i64 c = 0; c < nclu; c += PG) {
-            Stage st[PG];
-#pragma unroll
-            for (int g = 0; g < PG; g++) load(min(c + g, nclu - 1), st[g]);
-#pragma unroll
-            for (int g = 0; g < PG; g++)
-                if (c + g < nclu) consume(st[g]);
-        }
-    } else {
-        for (i64 c = 0; c < nclu; c++) {
-            Stage st;
-            load(c, st);
-            consume(st);
-        }
+    for (i64 c = 0; c < nclu; c++) {
+        Stage st;
+        load(c, st);
+        consume(st);
     }
 #pragma unroll
     for (int q = 0; q < R; q++)
